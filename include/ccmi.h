@@ -1,0 +1,269 @@
+/*
+ * ccmi.h - C ABI of libccmi, proximal-distance convex clustering on MI355X.
+ *
+ * The method (Chen, Chi, Ranola, Lange, "Convex Clustering: An Attractive
+ * Alternative to Hierarchical Clustering"):
+ *   minimise f_mu(U) = 1/2 sum_{(i,f) observed} (x_if - u_if)^2
+ *                      + mu sum_{i<j} w_ij ||u_i - u_j||          (eq_lindsten,
+ *                                                          eq_missing_analog)
+ * by the proximal-distance MM algorithm of Section "The Proximal Distance
+ * Algorithm": split v_ij = u_i - u_j (eq_proxdist), smooth the distance to the
+ * constraint set by eps (dist_eps), majorise twice (first_surrogate,
+ * sqrt_root_majorization, second_surrogate), and iterate
+ *   projection (A, D A) = P_C(U, V)         block-descent projection
+ *   d = sqrt(||U - A||^2 + ||V - D A||^2 + eps)
+ *   v_e <- max(1 - mu w_e d / (rho ||b_e||), 0) b_e,  b = D A     (V update)
+ *   u_i <- (d y_i + rho a_i) / (d + rho), y = x observed, u elsewhere
+ *                                                   (U update, Missing Data)
+ * The projection is approximated by one Jacobi sweep of the paper's block
+ * update per MM iteration, started from the previous projection; the fixed
+ * points are those of the exact projection.
+ *
+ * Conventions
+ *   - Every function returns a cc_status and never throws.  On an error
+ *     cc_last_error_message() (thread-local) describes it.
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary host memory.
+ *   - Matrices are row-major, one row per case (point), with a leading
+ *     dimension in elements (ldx >= p).  This is the same byte layout as the
+ *     paper's p x n column-major X with cases as columns.
+ *   - Edges are unordered pairs {i, j} with positive weight, given once as
+ *     (ei[e], ej[e]) with 0 <= ei[e] < ej[e] < n, 0-based, no duplicates
+ *     (Methods: E is the set of pairs with w_ij > 0).
+ *   - Work is enqueued on the stream given at creation (a hipStream_t passed
+ *     as void*, NULL = the null stream).  Functions that return results to
+ *     host memory synchronise that stream; results written to device memory
+ *     are ordered on the stream and the caller synchronises.
+ *   - A cc_problem_t is used by one host thread at a time.  Distinct problems
+ *     may run concurrently on distinct streams.
+ *   - Arguments are validated on the host before anything is launched; on
+ *     CC_ERR_INVALID_ARG nothing has been written.
+ */
+#ifndef CCMI_H
+#define CCMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cc_status;
+enum {
+  CC_OK = 0,
+  CC_ERR_INVALID_ARG = 1,   /* bad argument; nothing was written            */
+  CC_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed             */
+  CC_ERR_HIP = 3,           /* a HIP runtime call failed                    */
+  CC_ERR_NUMERIC = 4,       /* d or the objective became non-finite         */
+  CC_ERR_STATE = 5          /* call not valid in the problem's state        */
+};
+
+/* Element type of caller-supplied data matrices. */
+enum { CC_DTYPE_F32 = 0, CC_DTYPE_F64 = 1 };
+
+/* Storage precision of the solver state.
+ *   CC_PREC_F32   U, A and the pair sweep in FP32; reductions FP64.
+ *   CC_PREC_MIXED U and A (point-level state) in FP64, an FP32 copy of A for
+ *                 the pair sweep, which runs in FP32; reductions, d, the
+ *                 objective, the convergence test and every fusion decision
+ *                 in FP64.  Default.
+ *   CC_PREC_F64   everything FP64. */
+enum { CC_PREC_F32 = 0, CC_PREC_MIXED = 1, CC_PREC_F64 = 2 };
+
+typedef struct cc_problem *cc_problem_t;
+
+/* Solver options.  Fill with cc_default_opts() and then change fields.
+ *   eta         accuracy knob: eps = (eta * rho)^2 when eps <= 0.  The MM
+ *               fixed point lies O(eta) from the exact minimiser of f_mu.
+ *   rho         penalty constant of the proximal-distance method ("rho bigger
+ *               than a Lipschitz constant"); <= 0 selects
+ *               rho = 2 sqrt(||M o (X - xbar)||^2 + mu^2 sum_e w_e^2), a bound
+ *               on the multiplier norm at the optimum.  Recomputed per mu.
+ *   eps         smoothing constant of dist_eps; <= 0 selects (eta rho)^2.
+ *   tol         stop after MM iteration m >= 2 when
+ *                 sqrt(||U_{m+1}-U_m||^2 + ||A_m - A_{m-1}||^2)
+ *                    <= tol * eta * max(1, ||U_{m+1}||_F)
+ *               with eta = sqrt(eps)/rho; 0 disables the test.
+ *   max_iter    MM iteration cap per mu (not an error when reached).
+ *   check_every iterations enqueued between host checks of the stop flag.
+ *   warm_start  1: start from the problem's current state (the previous
+ *               solve's final state, or an imported one); 0: start from the
+ *               initial state U = A = X-tilde, V = D X-tilde.
+ *   record_objective  1: keep the objective of every iteration
+ *               (cc_get_trace). */
+typedef struct {
+  int32_t struct_size; /* sizeof(cc_solve_opts) */
+  double eta;          /* default 1e-2 */
+  double rho;          /* default 0 (auto) */
+  double eps;          /* default 0 (auto) */
+  double tol;          /* default 1e-6 */
+  int32_t max_iter;    /* default 200000 */
+  int32_t check_every; /* default 256 */
+  int32_t warm_start;  /* default 1 */
+  int32_t record_objective; /* default 0 */
+} cc_solve_opts;
+
+/* Result of one solve (one mu).  objective and d belong to the last MM
+ * iteration performed; rel_change is the quantity compared in the stopping
+ * test divided by max(1, ||U||_F). */
+typedef struct {
+  int32_t iters;      /* MM iterations performed */
+  int32_t converged;  /* 1 if the stopping test passed */
+  int32_t n_clusters; /* connected components of the fused edges */
+  int32_t status;     /* cc_status of this solve */
+  double gamma;       /* mu */
+  double objective;   /* F = loss + mu sum w ||v|| + rho d */
+  double d;           /* smoothed distance d of the last iteration */
+  double rel_change;
+  double rho;
+  double eps;
+  double seconds;     /* wall time of the solve, host clock */
+} cc_solve_info;
+
+const char *cc_status_string(cc_status s);
+const char *cc_last_error_message(void);
+void cc_default_opts(cc_solve_opts *opts);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t cc_version(void);
+
+/* ---------------------------------------------------------------------
+ * Problem lifetime
+ * ---------------------------------------------------------------------
+ * cc_problem_create: copy a clustering problem into library-owned device
+ * memory and set the initial state.
+ *   n, p        cases and predictors, both >= 1.
+ *   x_dtype     CC_DTYPE_F32 or CC_DTYPE_F64 for X.
+ *   X           device, n rows of ldx elements; only observed entries are
+ *               read (missing ones may hold anything, NaN included).
+ *   mask        device uint8, n rows of ldm bytes, nonzero = observed
+ *               (the index set Gamma of eq_missing_analog); NULL = all
+ *               observed.
+ *   n_edges     |E| >= 0.  ei, ej: device int32 endpoint arrays; w: device
+ *               float64 weights, finite and > 0 (eq_weighting, or any prior
+ *               weights).
+ *   precision   CC_PREC_* for the solver state.
+ *   stream      hipStream_t for all work of this problem.
+ * The inputs are copied; the function synchronises the stream before
+ * returning, so the caller may free them afterwards.  Observed X must be
+ * finite.  On success *out owns the device state until cc_problem_destroy. */
+cc_status cc_problem_create(int64_t n, int64_t p, int32_t x_dtype,
+                            const void *X, int64_t ldx, const uint8_t *mask,
+                            int64_t ldm, int64_t n_edges, const int32_t *ei,
+                            const int32_t *ej, const double *w,
+                            int32_t precision, void *stream,
+                            cc_problem_t *out);
+cc_status cc_problem_destroy(cc_problem_t prob);
+/* Dimensions (host outputs, any may be NULL). */
+cc_status cc_problem_dims(cc_problem_t prob, int64_t *n, int64_t *p,
+                          int64_t *n_edges, int32_t *precision);
+
+/* ---------------------------------------------------------------------
+ * Solving
+ * ---------------------------------------------------------------------
+ * cc_solve: run the MM iteration at mu = gamma >= 0 until the stopping test
+ * passes or max_iter iterations are done.  opts may be NULL (defaults).
+ * info (host, may be NULL) is filled synchronously.  Afterwards the state
+ * holds U, the factored V and the fusion pattern of the final iterate.
+ * Returns CC_ERR_NUMERIC if d or the objective became non-finite. */
+cc_status cc_solve(cc_problem_t prob, double gamma, const cc_solve_opts *opts,
+                   cc_solve_info *info);
+
+/* cc_solve_path: solve for gammas[0..n_gamma-1] (host) in the given order,
+ * each warm-started from the previous one's final state (the first one
+ * from the current state if opts->warm_start, else from the initial state).
+ * labels (device int32, n_gamma*n, may be NULL): row g holds the cluster
+ * label of every case after gammas[g], the smallest case index of its
+ * cluster.  U_path (device float32, n_gamma rows of n*p, row-major with
+ * leading dimension p, may be NULL): the centres after each gamma.
+ * infos (host, n_gamma entries, may be NULL). */
+cc_status cc_solve_path(cc_problem_t prob, int32_t n_gamma,
+                        const double *gammas, const cc_solve_opts *opts,
+                        int32_t *labels, float *U_path, cc_solve_info *infos);
+
+/* ---------------------------------------------------------------------
+ * Results
+ * --------------------------------------------------------------------- */
+/* Centres U of the current state into device memory of out_dtype, n rows of
+ * ldu elements. */
+cc_status cc_get_U(cc_problem_t prob, int32_t out_dtype, void *U, int64_t ldu);
+/* Cluster labels (device int32, n): connected components of the fused edges
+ * (v_e = 0 after the last V update), each labelled by its smallest case
+ * index.  n_clusters (host, may be NULL) receives the count. */
+cc_status cc_get_labels(cc_problem_t prob, int32_t *labels,
+                        int32_t *n_clusters);
+/* Fused flag per input edge, in input order (device uint8, n_edges). */
+cc_status cc_get_fused_edges(cc_problem_t prob, uint8_t *fused);
+/* Objective of every iteration of the last solve with record_objective = 1
+ * (host float64, up to cap values); *count receives the number stored. */
+cc_status cc_get_trace(cc_problem_t prob, double *F, int64_t cap,
+                       int64_t *count);
+
+/* ---------------------------------------------------------------------
+ * State checkpoint (warm starts across processes or problems)
+ * ---------------------------------------------------------------------
+ * The state is (U, s, A'), with V = diag(s) D A'.  cc_state_size gives the
+ * byte size of the serialised state; export writes it to host memory,
+ * import reads it back into a problem of the same n, p, edge set and
+ * precision (CC_ERR_INVALID_ARG otherwise).  cc_reset_state returns to the
+ * initial state. */
+cc_status cc_state_size(cc_problem_t prob, size_t *bytes);
+cc_status cc_export_state(cc_problem_t prob, void *buf, size_t bytes);
+cc_status cc_import_state(cc_problem_t prob, const void *buf, size_t bytes);
+cc_status cc_reset_state(cc_problem_t prob);
+/* Set the state from device arrays: U and A' (float64, n rows of ld) and s
+ * (float64, n_edges, in input edge order, each in [0, 1]). */
+cc_status cc_set_state(cc_problem_t prob, const double *U, const double *A,
+                       int64_t ld, const double *s);
+/* Read the state into device arrays of the same form. */
+cc_status cc_get_state(cc_problem_t prob, double *U, double *A, int64_t ld,
+                       double *s);
+
+/* ---------------------------------------------------------------------
+ * Weights and input preparation
+ * ---------------------------------------------------------------------
+ * cc_build_knn_weights: the weights of eq_weighting,
+ *   w_ij = 1{i ~_k j} exp(-phi d_ij^2),  d_ij = ||x_i - x_j||,
+ * where i ~_k j when j is among the k nearest neighbours of i or i among
+ * those of j (self excluded, distance ties to the lower index).  Distances
+ * use the matrix with missing entries replaced by observed column means.
+ * Candidates are ranked with a Gram matrix product on the matrix cores and
+ * then re-ranked with exact FP64 distances.
+ *   k           1 <= k < n.
+ *   phi         >= 0 literal; < 0 means |phi| / median(d^2 over the edge
+ *               set), the lower median.
+ *   normalize   1: scale the weights to sum to 1 over the edge set (the
+ *               paper's normalisation, equivalent to rescaling mu).
+ *   ei, ej, w   device outputs with room for capacity edges (n*k always
+ *               suffices); edges come out sorted by (ei, ej), ei < ej.
+ *   n_edges     host output, |E|.  phi_used: host output, may be NULL.
+ * Supports n <= 16384. */
+cc_status cc_build_knn_weights(int64_t n, int64_t p, int32_t x_dtype,
+                               const void *X, int64_t ldx,
+                               const uint8_t *mask, int64_t ldm, int32_t k,
+                               double phi, int32_t normalize, int32_t *ei,
+                               int32_t *ej, double *w, int64_t capacity,
+                               int64_t *n_edges, double *phi_used,
+                               void *stream);
+
+/* cc_standardize_columns: in place on device X (x_dtype, n rows of ldx),
+ * each column to mean 0 and variance 1 over its observed entries
+ * (divisor = observed count); a constant column becomes 0; missing entries
+ * are left untouched.  The paper advises this when predictors have widely
+ * different scales (Methods, after eq_lindsten). */
+cc_status cc_standardize_columns(int64_t n, int64_t p, int32_t x_dtype,
+                                 void *X, int64_t ldx, const uint8_t *mask,
+                                 int64_t ldm, void *stream);
+
+/* cc_components: connected components of the subgraph of edges with
+ * keep[e] != 0 (device uint8, may be NULL = all), labels (device int32, n)
+ * = smallest index in each component; n_components host output. */
+cc_status cc_components(int64_t n, int64_t n_edges, const int32_t *ei,
+                        const int32_t *ej, const uint8_t *keep,
+                        int32_t *labels, int32_t *n_components, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCMI_H */
