@@ -81,17 +81,21 @@ typedef struct cc_problem *cc_problem_t;
  *               rho = 2 sqrt(||M o (X - xbar)||^2 + mu^2 sum_e w_e^2), a bound
  *               on the multiplier norm at the optimum.  Recomputed per mu.
  *   eps         smoothing constant of dist_eps; <= 0 selects (eta rho)^2.
- *   tol         stop after MM iteration m >= 2 when
- *                 sqrt(||U_{m+1}-U_m||^2 + ||A_m - A_{m-1}||^2)
+ *   tol         stop after MM iteration m >= 2, taken when m+1 is a
+ *               multiple of test_every = K, if
+ *                 sqrt(||U_{m+1}-U_{m+1-K}||^2 + ||A_m - A_{m-K}||^2) / K
  *                    <= tol * eta * max(1, ||U_{m+1}||_F)
- *               with eta = sqrt(eps)/rho; 0 disables the test.
+ *               with eta = sqrt(eps)/rho; 0 disables the test.  The paper
+ *               leaves the stopping rule open; the window K averages out
+ *               rounding-level jitter of reduced-precision state.
  *   max_iter    MM iteration cap per mu (not an error when reached).
  *   check_every iterations enqueued between host checks of the stop flag.
  *   warm_start  1: start from the problem's current state (the previous
  *               solve's final state, or an imported one); 0: start from the
  *               initial state U = A = X-tilde, V = D X-tilde.
  *   record_objective  1: keep the objective of every iteration
- *               (cc_get_trace). */
+ *               (cc_get_trace).
+ *   test_every  the window K of the stopping test, >= 1 (default 64). */
 typedef struct {
   int32_t struct_size; /* sizeof(cc_solve_opts) */
   double eta;          /* default 1e-2 */
@@ -102,6 +106,7 @@ typedef struct {
   int32_t check_every; /* default 256 */
   int32_t warm_start;  /* default 1 */
   int32_t record_objective; /* default 0 */
+  int32_t test_every;  /* default 64 */
 } cc_solve_opts;
 
 /* Result of one solve (one mu).  objective and d belong to the last MM
@@ -198,6 +203,18 @@ cc_status cc_get_fused_edges(cc_problem_t prob, uint8_t *fused);
  * (host float64, up to cap values); *count receives the number stored. */
 cc_status cc_get_trace(cc_problem_t prob, double *F, int64_t cap,
                        int64_t *count);
+
+/* ---------------------------------------------------------------------
+ * Kernel timing
+ * ---------------------------------------------------------------------
+ * cc_profile: sample_every > 0 brackets the three kernels of every
+ * sample_every-th MM iteration with HIP events on the problem's stream and
+ * accumulates their durations; 0 turns sampling off.  Enabling clears the
+ * statistics.  cc_kernel_stats (host outputs, 3 entries each, in the order
+ * point sweep, edge sweep, edge reduction) returns the mean duration in
+ * milliseconds and the number of sampled launches. */
+cc_status cc_profile(cc_problem_t prob, int32_t sample_every);
+cc_status cc_kernel_stats(cc_problem_t prob, double *avg_ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------
  * State checkpoint (warm starts across processes or problems)

@@ -1,0 +1,12 @@
+"""paper_1409_2065_amd: proximal-distance convex clustering on MI355X.
+
+The compute path is libccmi.so (hand-written HIP kernels for gfx950) behind
+the C ABI in include/ccmi.h; this package is a thin ctypes binding over it
+that takes torch device tensors.  Build with
+``python -m paper_1409_2065_amd.build``.
+"""
+from ._lib import CCError, LIB_PATH, load  # noqa: F401
+from .api import PRECISIONS, Problem, build_knn_weights, components, standardize_columns  # noqa: F401
+
+__all__ = ["Problem", "build_knn_weights", "standardize_columns", "components", "CCError",
+           "PRECISIONS", "load", "LIB_PATH"]

@@ -1,0 +1,230 @@
+"""Python face of libccmi on torch device tensors.
+
+Every function marshals arguments (device pointers, sizes, the current HIP
+stream) into one C-ABI call of libccmi; PyTorch only supplies device memory
+and streams.  Inputs must be contiguous tensors on the current HIP device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CCError, check, default_opts
+
+PRECISIONS = {"f32": _lib.CC_PREC_F32, "mixed": _lib.CC_PREC_MIXED, "f64": _lib.CC_PREC_F64}
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t))
+    if dtype is not None and t.dtype != dtype:
+        t = t.to(dtype)
+    if not t.is_cuda:
+        t = t.cuda()
+    return t.contiguous()
+
+
+def _xdtype(X: torch.Tensor) -> int:
+    if X.dtype == torch.float32:
+        return _lib.CC_DTYPE_F32
+    if X.dtype == torch.float64:
+        return _lib.CC_DTYPE_F64
+    raise TypeError("X must be float32 or float64")
+
+
+def _mask(mask, shape):
+    if mask is None:
+        return None
+    m = _dev(mask)
+    if m.dtype != torch.uint8:
+        m = m.to(torch.uint8)
+    if tuple(m.shape) != tuple(shape):
+        raise ValueError("mask shape must equal X shape")
+    return m.contiguous()
+
+
+class Problem:
+    """A clustering problem resident on the GPU (cc_problem_create)."""
+
+    def __init__(self, X, mask=None, edges=None, w=None, precision: str = "mixed"):
+        X = _dev(X)
+        if X.dtype not in (torch.float32, torch.float64):
+            X = X.to(torch.float32)
+        n, p = X.shape
+        m = _mask(mask, X.shape)
+        if edges is None:
+            edges = torch.zeros((0, 2), dtype=torch.int32)
+        e = _dev(edges, torch.int32).reshape(-1, 2)
+        ei = e[:, 0].contiguous()
+        ej = e[:, 1].contiguous()
+        wt = _dev(w if w is not None else torch.zeros(0), torch.float64).reshape(-1)
+        self._keep = (X, m, ei, ej, wt)
+        self.n, self.p, self.E = int(n), int(p), int(e.shape[0])
+        self.precision = precision
+        lib = _lib.load()
+        h = C.c_void_p()
+        check(lib.cc_problem_create(n, p, _xdtype(X), _ptr(X), p, _ptr(m), p, self.E,
+                                    _ptr(ei), _ptr(ej), _ptr(wt), PRECISIONS[precision],
+                                    C.c_void_p(_stream()), C.byref(h)))
+        self._h = h
+        self._keep = None
+
+    # -- lifetime --
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().cc_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- solving --
+    def solve(self, gamma: float, **opts) -> dict:
+        o = default_opts(**opts)
+        info = _lib.SolveInfo()
+        check(_lib.load().cc_solve(self._h, float(gamma), C.byref(o), C.byref(info)))
+        return info.as_dict()
+
+    def solve_path(self, gammas: Sequence[float], labels: bool = True, U_path: bool = False, **opts):
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+        G = g.size
+        o = default_opts(**opts)
+        infos = (_lib.SolveInfo * max(G, 1))()
+        lab = torch.empty((G, self.n), dtype=torch.int32, device="cuda") if labels else None
+        up = torch.empty((G, self.n, self.p), dtype=torch.float32, device="cuda") if U_path else None
+        check(_lib.load().cc_solve_path(self._h, G, g.ctypes.data_as(_lib.P_f64), C.byref(o),
+                                        _ptr(lab), _ptr(up), infos))
+        return [infos[k].as_dict() for k in range(G)], lab, up
+
+    # -- results --
+    def U(self, dtype=torch.float32) -> torch.Tensor:
+        out = torch.empty((self.n, self.p), dtype=dtype, device="cuda")
+        dt = _lib.CC_DTYPE_F32 if dtype == torch.float32 else _lib.CC_DTYPE_F64
+        check(_lib.load().cc_get_U(self._h, dt, _ptr(out), self.p))
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def labels(self):
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        k = C.c_int32()
+        check(_lib.load().cc_get_labels(self._h, _ptr(out), C.byref(k)))
+        return out, int(k.value)
+
+    def fused_edges(self) -> torch.Tensor:
+        out = torch.empty(max(self.E, 1), dtype=torch.uint8, device="cuda")
+        check(_lib.load().cc_get_fused_edges(self._h, _ptr(out)))
+        torch.cuda.current_stream().synchronize()
+        return out[: self.E]
+
+    def trace(self, cap: int = 1 << 22) -> np.ndarray:
+        buf = np.empty(cap, dtype=np.float64)
+        cnt = C.c_int64()
+        check(_lib.load().cc_get_trace(self._h, buf.ctypes.data_as(_lib.P_f64), cap, C.byref(cnt)))
+        return buf[: cnt.value].copy()
+
+    # -- kernel timing --
+    def profile(self, sample_every: int) -> None:
+        check(_lib.load().cc_profile(self._h, int(sample_every)))
+
+    def kernel_stats(self):
+        ms = (C.c_double * 3)()
+        cnt = (C.c_int64 * 3)()
+        check(_lib.load().cc_kernel_stats(self._h, ms, cnt))
+        names = ("point_sweep", "edge_sweep", "edge_reduce")
+        return {nm: {"avg_ms": ms[q], "launches": cnt[q]} for q, nm in enumerate(names)}
+
+    # -- state --
+    def export_state(self) -> bytes:
+        sz = C.c_size_t()
+        check(_lib.load().cc_state_size(self._h, C.byref(sz)))
+        buf = C.create_string_buffer(sz.value)
+        check(_lib.load().cc_export_state(self._h, buf, sz.value))
+        return buf.raw
+
+    def import_state(self, data: bytes) -> None:
+        buf = C.create_string_buffer(data, len(data))
+        check(_lib.load().cc_import_state(self._h, buf, len(data)))
+
+    def reset_state(self) -> None:
+        check(_lib.load().cc_reset_state(self._h))
+
+    def set_state(self, U, A, s) -> None:
+        U = _dev(U, torch.float64)
+        A = _dev(A, torch.float64)
+        s = _dev(s, torch.float64).reshape(-1)
+        check(_lib.load().cc_set_state(self._h, _ptr(U), _ptr(A), self.p, _ptr(s)))
+
+    def get_state(self):
+        U = torch.empty((self.n, self.p), dtype=torch.float64, device="cuda")
+        A = torch.empty((self.n, self.p), dtype=torch.float64, device="cuda")
+        s = torch.empty(max(self.E, 1), dtype=torch.float64, device="cuda")
+        check(_lib.load().cc_get_state(self._h, _ptr(U), _ptr(A), self.p, _ptr(s)))
+        torch.cuda.current_stream().synchronize()
+        return U, A, s[: self.E]
+
+
+def build_knn_weights(X, mask=None, k: int = 10, phi: float = 0.5, normalize: bool = False):
+    """cc_build_knn_weights: returns (edges (E, 2) int32, w (E,) float64,
+    phi_used), on the device."""
+    X = _dev(X)
+    n, p = X.shape
+    m = _mask(mask, X.shape)
+    cap = n * k
+    ei = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ej = torch.empty(cap, dtype=torch.int32, device="cuda")
+    w = torch.empty(cap, dtype=torch.float64, device="cuda")
+    ne = C.c_int64()
+    phi_used = C.c_double()
+    check(_lib.load().cc_build_knn_weights(n, p, _xdtype(X), _ptr(X), p, _ptr(m), p, int(k), float(phi),
+                                           1 if normalize else 0, _ptr(ei), _ptr(ej), _ptr(w), cap,
+                                           C.byref(ne), C.byref(phi_used), C.c_void_p(_stream())))
+    E = ne.value
+    return torch.stack([ei[:E], ej[:E]], dim=1).contiguous(), w[:E].contiguous(), phi_used.value
+
+
+def standardize_columns(X: torch.Tensor, mask=None) -> torch.Tensor:
+    """cc_standardize_columns, in place on X; returns X."""
+    if not (X.is_cuda and X.is_contiguous()):
+        raise ValueError("X must be a contiguous device tensor")
+    m = _mask(mask, X.shape)
+    n, p = X.shape
+    check(_lib.load().cc_standardize_columns(n, p, _xdtype(X), _ptr(X), p, _ptr(m), p,
+                                             C.c_void_p(_stream())))
+    return X
+
+
+def components(n: int, edges, keep=None):
+    """cc_components: labels (n,) int32 (min index per component) and count."""
+    e = _dev(edges, torch.int32).reshape(-1, 2)
+    ei = e[:, 0].contiguous()
+    ej = e[:, 1].contiguous()
+    kp = None if keep is None else _dev(keep, torch.uint8)
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    cnt = C.c_int32()
+    check(_lib.load().cc_components(n, e.shape[0], _ptr(ei), _ptr(ej), _ptr(kp), _ptr(lab), C.byref(cnt),
+                                    C.c_void_p(_stream())))
+    return lab, int(cnt.value)
+
+
+__all__ = ["Problem", "build_knn_weights", "standardize_columns", "components", "CCError", "PRECISIONS"]

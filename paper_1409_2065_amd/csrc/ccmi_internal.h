@@ -1,0 +1,126 @@
+// Internal declarations shared by the libccmi translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ccmi.h"
+
+namespace ccmi {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
+constexpr int kMaxBlocks = 2048; // grid cap for the grid-stride sweeps
+constexpr int kPointSums = 6;    // per-block FP64 partial sums of the point pass
+constexpr int kEdgeSums = 3;     // per-block FP64 partial sums of the edge pass
+
+// Device-resident iteration scalars.  Written by the host only through the
+// set-parameters kernel; read by every kernel of an iteration; advanced by
+// the last block of the edge-reduction kernel.
+struct DevScalars {
+  // per-solve constants
+  double mu, rho, eps, thr;  // thr = tol * eta (0 disables the stop test)
+  int max_iter, record, K, mode_pad1;  // K = stop-test window
+  // iteration state
+  int m;          // MM iteration index within the current solve
+  int pa;         // buffer index holding A_{m-1} (and its edge norms)
+  int done, converged, status, iters;
+  double d_prev;  // d_{m-1}
+  double dA_prev; // ||A_{m-1} - A_{m-1-K}||^2 of the last A window
+  double F_cur;   // F_{m-1} once iteration m-1 has finished
+  double F_last, d_last, rel_last;
+  unsigned int counter; // last-block-done counter of the reduction kernel
+  unsigned int pad2;
+};
+
+enum Prec { kF32 = CC_PREC_F32, kMixed = CC_PREC_MIXED, kF64 = CC_PREC_F64 };
+
+struct Problem {
+  int64_t n = 0, p = 0, E = 0, ld = 0;
+  int precision = kMixed;
+  hipStream_t stream = nullptr;
+  int ntile = 1;      // feature tiles of width tile_w
+  int tile_w = 256;   // features per tile (64 lanes x vec)
+  int vec = 4;
+  // device buffers
+  void *X = nullptr;         // n x ld, float (f32/mixed) or double (f64)
+  uint8_t *M = nullptr;      // n x ld or null
+  void *U = nullptr;         // n x ld, state type
+  void *A[2] = {nullptr, nullptr};  // n x ld, state type
+  void *G[2] = {nullptr, nullptr};  // gather mirrors (== A when no mirror)
+  void *Usnap = nullptr, *Asnap = nullptr;  // stop-test window snapshots
+  int32_t *rowptr = nullptr, *col = nullptr, *eid = nullptr, *uptr = nullptr;
+  int32_t *ei = nullptr, *ej = nullptr;
+  double *w = nullptr, *s = nullptr, *nb[2] = {nullptr, nullptr};
+  double *part = nullptr;    // E x ntile edge partials
+  double *psum = nullptr;    // kMaxBlocks x 8 point partials
+  double *esum = nullptr;    // kMaxBlocks x 4 edge partials
+  double *trace = nullptr;   // objective per iteration (record mode)
+  int64_t trace_cap = 0, trace_count = 0;
+  DevScalars *sc = nullptr;
+  DevScalars *sc_host = nullptr; // pinned mirror
+  int32_t *flag_host = nullptr;  // pinned
+  int32_t *ncl_dev = nullptr;
+  // host-side constants
+  double dev2 = 0.0;   // ||M o (X - xbar)||^2
+  double w2 = 0.0;     // sum_e w_e^2
+  int64_t max_deg = 0;
+  bool has_mask = false;
+  bool state_valid = true;
+  // sampled kernel timing (cc_profile)
+  int prof_every = 0;
+  int64_t prof_iter = 0;
+  std::vector<hipEvent_t> prof_events;  // 4 per sampled iteration
+  size_t prof_used = 0;                 // event sets recorded, not yet harvested
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_n[3] = {0, 0, 0};
+};
+
+// ---- error reporting (thread-local message) ----
+void set_error(const std::string &msg);
+cc_status hip_fail(hipError_t e, const char *what);
+#define CC_HIP(call)                                  \
+  do {                                                \
+    hipError_t _e = (call);                           \
+    if (_e != hipSuccess) return ::ccmi::hip_fail(_e, #call); \
+  } while (0)
+
+// ---- solver (solver.hip) ----
+cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
+                         int64_t ldx, const uint8_t *mask, int64_t ldm,
+                         int64_t n_edges, const int32_t *ei, const int32_t *ej,
+                         const double *w, int32_t precision, hipStream_t stream,
+                         Problem **out);
+void problem_free(Problem *P);
+cc_status reset_state(Problem *P);
+cc_status solve(Problem *P, double gamma, const cc_solve_opts &o,
+                cc_solve_info *info);
+cc_status write_labels(Problem *P, int32_t *labels, int32_t *ncl_host);
+cc_status copy_U(Problem *P, int32_t out_dtype, void *dst, int64_t ldu);
+cc_status get_fused(Problem *P, uint8_t *fused);
+cc_status set_state(Problem *P, const double *U, const double *A, int64_t ld,
+                    const double *s);
+cc_status get_state(Problem *P, double *U, double *A, int64_t ld, double *s);
+cc_status profile(Problem *P, int32_t sample_every);
+cc_status harvest_profile(Problem *P);
+cc_status components(int64_t n, int64_t E, const int32_t *ei,
+                     const int32_t *ej, const uint8_t *keep, const double *s,
+                     int32_t *labels, int32_t *ncl_dev, hipStream_t stream);
+
+// ---- weights and preparation (knn.hip) ----
+cc_status build_knn_weights(int64_t n, int64_t p, int32_t x_dtype,
+                            const void *X, int64_t ldx, const uint8_t *mask,
+                            int64_t ldm, int32_t k, double phi,
+                            int32_t normalize, int32_t *ei, int32_t *ej,
+                            double *w, int64_t capacity, int64_t *n_edges,
+                            double *phi_used, hipStream_t stream);
+cc_status standardize_columns(int64_t n, int64_t p, int32_t x_dtype, void *X,
+                              int64_t ldx, const uint8_t *mask, int64_t ldm,
+                              hipStream_t stream);
+
+}  // namespace ccmi

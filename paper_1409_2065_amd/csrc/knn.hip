@@ -1,0 +1,525 @@
+// k-nearest-neighbour Gaussian-kernel weights (Methods, "Calibration of
+// Weights", eq_weighting) and column standardisation on gfx950.
+//
+// Pipeline of cc_build_knn_weights:
+//   1. observed column means; X-tilde = X with missing entries replaced by
+//      them, kept in FP32 (for ranking) and FP64 (for exact distances);
+//   2. Gram matrix G = X~ X~^T on the matrix cores (v_mfma_f32_16x16x4_f32),
+//      d2_ij = |x_i|^2 + |x_j|^2 - 2 G_ij in FP32 for every pair;
+//   3. per row, a bitonic sort in LDS of (d2, j) keys, self excluded, ties to
+//      the lower index, keeps the K = k + margin best candidates;
+//   4. exact FP64 distances of the candidates, re-sorted by (d2, j), keep k;
+//   5. the relation i ~_k j (either direction) as a bitmap, counted and
+//      prefix-summed per row, written out as sorted edges (i < j);
+//   6. exact FP64 d2 per edge, phi (literal or |phi| / lower median d2),
+//      w = exp(-phi d2), optional normalisation to sum 1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "ccmi_internal.h"
+
+namespace ccmi {
+
+static inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------- column stats
+template <typename TI>
+__global__ void k_col_moments(int n, int p, const TI *X, int64_t ldx, const uint8_t *M,
+                              int64_t ldm, double *mean, double *sd, int *nonfinite) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= p) return;
+  double sum = 0.0;
+  int cnt = 0, bad = 0;
+  for (int i = 0; i < n; ++i) {
+    if (M && M[(size_t)i * ldm + f] == 0) continue;
+    const double x = (double)X[(size_t)i * ldx + f];
+    if (!isfinite(x)) { ++bad; continue; }
+    sum += x; ++cnt;
+  }
+  const double mu = cnt > 0 ? sum / cnt : 0.0;
+  double ss = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (M && M[(size_t)i * ldm + f] == 0) continue;
+    const double x = (double)X[(size_t)i * ldx + f];
+    if (!isfinite(x)) continue;
+    ss += (x - mu) * (x - mu);
+  }
+  mean[f] = mu;
+  if (sd) sd[f] = cnt > 0 ? sqrt(ss / cnt) : 0.0;
+  if (bad) atomicAdd(nonfinite, bad);
+}
+
+template <typename TI>
+__global__ void k_standardize(int n, int p, TI *X, int64_t ldx, const uint8_t *M, int64_t ldm,
+                              const double *mean, const double *sd) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * p) return;
+  const int i = (int)(idx / p), f = (int)(idx % p);
+  if (M && M[(size_t)i * ldm + f] == 0) return;
+  const double s = sd[f];
+  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  const double x = (double)X[(size_t)i * ldx + f];
+  X[(size_t)i * ldx + f] = (TI)((x - mean[f]) * inv);
+}
+
+// X-tilde in FP32 (n_pad x ldk, zero padded) and FP64 (n x p), and the FP32
+// squared row norms of the FP32 copy.
+template <typename TI>
+__global__ void k_impute(int n, int p, int n_pad, int ldk, const TI *X, int64_t ldx,
+                         const uint8_t *M, int64_t ldm, const double *mean, float *Xf,
+                         double *Xd) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n_pad * ldk) return;
+  const int i = (int)(idx / ldk), f = (int)(idx % ldk);
+  double v = 0.0;
+  if (i < n && f < p) {
+    const bool obs = M ? (M[(size_t)i * ldm + f] != 0) : true;
+    v = obs ? (double)X[(size_t)i * ldx + f] : mean[f];
+    Xd[(size_t)i * p + f] = v;
+  }
+  Xf[idx] = (float)v;
+}
+
+__global__ void k_rownorm(int n_pad, int ldk, const float *Xf, float *nrm) {
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int f = threadIdx.x; f < ldk; f += blockDim.x) {
+    const double v = Xf[(size_t)i * ldk + f];
+    acc = fma(v, v, acc);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  __shared__ double s[16];
+  if (threadIdx.x % kWave == 0) s[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += s[w];
+    nrm[i] = (float)t;
+  }
+}
+
+// ------------------------------------------------------------ MFMA Gram
+// Output tile 64 x 64 per block of 4 waves; wave w owns rows 16w..16w+15 and
+// all 64 columns as four 16 x 16 accumulators.  K is staged through LDS in
+// chunks of 16 features.  v_mfma_f32_16x16x4_f32 operand layout (wave64):
+// A element (row l%16, k l/16), B element (k l/16, col l%16), and result
+// register r of lane l holds (row 4*(l/16)+r, col l%16).
+constexpr int kGT = 64, kKC = 16;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_gram_d2(int n, int n_pad, int ldk, const float *Xf,
+                                                 const float *nrm, float *D2, int64_t ldd) {
+  __shared__ float As[kGT][kKC + 1];
+  __shared__ float Bs[kGT][kKC + 1];
+  const int bi = blockIdx.y * kGT, bj = blockIdx.x * kGT;
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  floatx4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < ldk; k0 += kKC) {
+    // 64 rows x 16 floats per operand: thread tid loads 4 consecutive floats
+    {
+      const int r = tid / 4, c4 = (tid % 4) * 4;
+      const float4 va = *reinterpret_cast<const float4 *>(Xf + (size_t)(bi + r) * ldk + k0 + c4);
+      const float4 vb = *reinterpret_cast<const float4 *>(Xf + (size_t)(bj + r) * ldk + k0 + c4);
+      As[r][c4 + 0] = va.x; As[r][c4 + 1] = va.y; As[r][c4 + 2] = va.z; As[r][c4 + 3] = va.w;
+      Bs[r][c4 + 0] = vb.x; Bs[r][c4 + 1] = vb.y; Bs[r][c4 + 2] = vb.z; Bs[r][c4 + 3] = vb.w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kKC; kk += 4) {
+      const float a = As[wave * 16 + lane % 16][kk + lane / 16];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float b = Bs[c * 16 + lane % 16][kk + lane / 16];
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = bi + wave * 16 + 4 * (lane / 16) + r;
+      const int j = bj + c * 16 + lane % 16;
+      if (i < n && j < n) D2[(size_t)i * ldd + j] = nrm[i] + nrm[j] - 2.0f * acc[c][r];
+    }
+  }
+}
+
+// Monotone map of a float to an unsigned key (handles negative values).
+__device__ inline uint32_t float_key(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Per row: bitonic sort of (key(d2) << 32 | j) in LDS; keep the first K.
+__global__ __launch_bounds__(1024) void k_row_candidates(int n, const float *D2, int64_t ldd,
+                                                         int npow2, int K, int32_t *cand) {
+  extern __shared__ unsigned long long keys[];
+  const int i = blockIdx.x;
+  for (int j = threadIdx.x; j < npow2; j += blockDim.x) {
+    unsigned long long key = ~0ull;
+    if (j < n && j != i) key = ((unsigned long long)float_key(D2[(size_t)i * ldd + j]) << 32) | (unsigned)j;
+    keys[j] = key;
+  }
+  __syncthreads();
+  for (int size = 2; size <= npow2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < npow2 / 2; t += blockDim.x) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = ((lo & size) == 0);
+        const unsigned long long a = keys[lo], b = keys[hi];
+        if ((a > b) == up) { keys[lo] = b; keys[hi] = a; }
+      }
+      __syncthreads();
+    }
+  }
+  for (int r = threadIdx.x; r < K; r += blockDim.x) cand[(size_t)i * K + r] = (int32_t)(keys[r] & 0xffffffffu);
+}
+
+// Exact FP64 squared distances of the candidates, then the k best by (d2, j).
+__global__ __launch_bounds__(256) void k_recheck(int n, int p, const double *Xd, int K, int k,
+                                                 const int32_t *cand, int32_t *knn) {
+  extern __shared__ double sd[];  // K doubles + K ints
+  int *sj = reinterpret_cast<int *>(sd + K);
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  for (int c = wave; c < K; c += nw) {
+    const int j = cand[(size_t)i * K + c];
+    double acc = 0.0;
+    for (int f = lane; f < p; f += kWave) {
+      const double d = Xd[(size_t)j * p + f] - Xd[(size_t)i * p + f];
+      acc = fma(d, d, acc);
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if (lane == 0) { sd[c] = acc; sj[c] = j; }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // selection of the k smallest (d2, j); K is small
+    for (int r = 0; r < k; ++r) {
+      int best = r;
+      for (int c = r + 1; c < K; ++c)
+        if (sd[c] < sd[best] || (sd[c] == sd[best] && sj[c] < sj[best])) best = c;
+      const double td = sd[r]; sd[r] = sd[best]; sd[best] = td;
+      const int tj = sj[r]; sj[r] = sj[best]; sj[best] = tj;
+      knn[(size_t)i * k + r] = sj[r];
+    }
+  }
+}
+
+__global__ void k_mark_pairs(int n, int k, int words, const int32_t *knn, uint32_t *bm) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * k) return;
+  const int i = (int)(idx / k);
+  const int j = knn[idx];
+  const int a = min(i, j), b = max(i, j);
+  atomicOr(&bm[(size_t)a * words + b / 32], 1u << (b % 32));
+}
+
+__global__ void k_row_counts(int n, int words, const uint32_t *bm, int32_t *cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  for (int w = 0; w < words; ++w) c += __popc(bm[(size_t)i * words + w]);
+  cnt[i] = c;
+}
+
+// Exclusive scan of n counts in one block (sequential chunks, fixed order).
+__global__ __launch_bounds__(1024) void k_scan(int n, const int32_t *cnt, int32_t *off, int64_t *total) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (n + nt - 1) / nt;
+  const int s0 = t * per, s1 = min(n, s0 + per);
+  int64_t acc = 0;
+  for (int i = s0; i < s1; ++i) acc += cnt[i];
+  part[t] = acc;
+  __syncthreads();
+  if (t == 0) {
+    int64_t run = 0;
+    for (int q = 0; q < nt; ++q) { const int64_t v = part[q]; part[q] = run; run += v; }
+    *total = run;
+  }
+  __syncthreads();
+  int64_t run = part[t];
+  for (int i = s0; i < s1; ++i) { off[i] = (int32_t)run; run += cnt[i]; }
+}
+
+__global__ void k_emit_edges(int n, int words, const uint32_t *bm, const int32_t *off,
+                             int32_t *ei, int32_t *ej) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int pos = off[i];
+  for (int w = 0; w < words; ++w) {
+    uint32_t bits = bm[(size_t)i * words + w];
+    while (bits) {
+      const int b = __ffs(bits) - 1;
+      bits &= bits - 1;
+      ei[pos] = i;
+      ej[pos] = w * 32 + b;
+      ++pos;
+    }
+  }
+}
+
+__global__ void k_edge_d2(int E, int p, const double *Xd, const int32_t *ei, const int32_t *ej,
+                          double *d2) {
+  const int e = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (e >= E) return;
+  const int i = ei[e], j = ej[e];
+  double acc = 0.0;
+  for (int f = lane; f < p; f += kWave) {
+    const double d = Xd[(size_t)j * p + f] - Xd[(size_t)i * p + f];
+    acc = fma(d, d, acc);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  if (lane == 0) d2[e] = acc;
+}
+
+// Lower median of E non-negative doubles by an 8-pass radix select on the
+// bit patterns (order-preserving for non-negative doubles).  One block.
+__global__ __launch_bounds__(1024) void k_lower_median(int E, const double *v, double *out) {
+  __shared__ unsigned int hist[256];
+  __shared__ unsigned long long prefix_s;
+  __shared__ long long rank_s;
+  if (threadIdx.x == 0) { prefix_s = 0ull; rank_s = (E - 1) / 2; }
+  __syncthreads();
+  for (int pass = 7; pass >= 0; --pass) {
+    for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    const unsigned long long prefix = prefix_s;
+    const int shift = pass * 8;
+    const unsigned long long himask = (pass == 7) ? 0ull : (~0ull << (shift + 8));
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+      const unsigned long long k = (unsigned long long)__double_as_longlong(v[e]);
+      if ((k & himask) == (prefix & himask)) atomicAdd(&hist[(k >> shift) & 0xffu], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long r = rank_s;
+      int digit = 0;
+      for (; digit < 256; ++digit) {
+        if (r < (long long)hist[digit]) break;
+        r -= hist[digit];
+      }
+      rank_s = r;
+      prefix_s = prefix | ((unsigned long long)digit << shift);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = __longlong_as_double((long long)prefix_s);
+}
+
+__global__ void k_weights(int E, const double *d2, const double *phi, double *w) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) w[e] = exp(-(*phi) * d2[e]);
+}
+
+__global__ __launch_bounds__(1024) void k_normalize(int E, double *w) {
+  __shared__ double s[1024];
+  double acc = 0.0;
+  const int per = (E + blockDim.x - 1) / blockDim.x;
+  const int e0 = threadIdx.x * per, e1 = min(E, e0 + per);
+  for (int e = e0; e < e1; ++e) acc += w[e];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  __shared__ double tot;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < (int)blockDim.x; ++q) t += s[q];
+    tot = t;
+  }
+  __syncthreads();
+  const double inv = 1.0 / tot;
+  for (int e = e0; e < e1; ++e) w[e] *= inv;
+}
+
+__global__ void k_phi_from_median(const double *med, double c, double *phi) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *phi = (*med > 0.0) ? c / *med : 0.0;
+}
+
+// ====================================================================== host
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  cc_status alloc(size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+      set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      return CC_ERR_OUT_OF_MEMORY;
+    }
+    return CC_OK;
+  }
+  template <typename T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+#define KN_TRY(x)               \
+  do {                          \
+    cc_status _s = (x);         \
+    if (_s != CC_OK) return _s; \
+  } while (0)
+
+template <typename TI>
+static cc_status knn_impl(int64_t n, int64_t p, const TI *X, int64_t ldx, const uint8_t *mask,
+                          int64_t ldm, int32_t k, double phi, int32_t normalize, int32_t *ei,
+                          int32_t *ej, double *w, int64_t capacity, int64_t *n_edges,
+                          double *phi_used, hipStream_t st) {
+  const int64_t n_pad = cdiv64(n, kGT) * kGT;
+  const int64_t ldk = cdiv64(p, kKC) * kKC;
+  const int K = (int)std::min<int64_t>(n - 1, (int64_t)k + std::max(16, (int)k));
+  int npow2 = 1;
+  while (npow2 < n) npow2 <<= 1;
+  const int words = (int)cdiv64(n, 32);
+
+  DevBuf mean, bad, Xf, Xd, nrm, D2, cand, knn, bm, cnt, off, total, d2, med, phid;
+  KN_TRY(mean.alloc(p * 8));
+  KN_TRY(bad.alloc(4));
+  KN_TRY(Xf.alloc((size_t)n_pad * ldk * 4));
+  KN_TRY(Xd.alloc((size_t)n * p * 8));
+  KN_TRY(nrm.alloc(n_pad * 4));
+  KN_TRY(D2.alloc((size_t)n * n * 4));
+  KN_TRY(cand.alloc((size_t)n * K * 4));
+  KN_TRY(knn.alloc((size_t)n * k * 4));
+  KN_TRY(bm.alloc((size_t)n * words * 4));
+  KN_TRY(cnt.alloc(n * 4));
+  KN_TRY(off.alloc(n * 4));
+  KN_TRY(total.alloc(8));
+  KN_TRY(med.alloc(8));
+  KN_TRY(phid.alloc(8));
+
+  CC_HIP(hipMemsetAsync(bad.p, 0, 4, st));
+  hipLaunchKernelGGL((k_col_moments<TI>), dim3((int)cdiv64(p, 256)), dim3(256), 0, st, (int)n,
+                     (int)p, X, ldx, mask, ldm, mean.as<double>(), (double *)nullptr, bad.as<int>());
+  int hbad = 0;
+  CC_HIP(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (hbad) { set_error("observed X has non-finite entries"); return CC_ERR_INVALID_ARG; }
+  hipLaunchKernelGGL((k_impute<TI>), dim3((int)cdiv64(n_pad * ldk, 256)), dim3(256), 0, st,
+                     (int)n, (int)p, (int)n_pad, (int)ldk, X, ldx, mask, ldm, mean.as<double>(),
+                     Xf.as<float>(), Xd.as<double>());
+  hipLaunchKernelGGL(k_rownorm, dim3((int)n_pad), dim3(256), 0, st, (int)n_pad, (int)ldk,
+                     Xf.as<float>(), nrm.as<float>());
+  const int gb = (int)(n_pad / kGT);
+  hipLaunchKernelGGL(k_gram_d2, dim3(gb, gb), dim3(256), 0, st, (int)n, (int)n_pad, (int)ldk,
+                     Xf.as<float>(), nrm.as<float>(), D2.as<float>(), (int64_t)n);
+  CC_HIP(hipGetLastError());
+  const size_t lds = (size_t)npow2 * 8;
+  CC_HIP(hipFuncSetAttribute((const void *)k_row_candidates,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_row_candidates, dim3((int)n), dim3(1024), lds, st, (int)n,
+                     D2.as<float>(), (int64_t)n, npow2, K, cand.as<int32_t>());
+  CC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_recheck, dim3((int)n), dim3(256), (size_t)K * 12, st, (int)n, (int)p,
+                     Xd.as<double>(), K, (int)k, cand.as<int32_t>(), knn.as<int32_t>());
+  CC_HIP(hipMemsetAsync(bm.p, 0, (size_t)n * words * 4, st));
+  hipLaunchKernelGGL(k_mark_pairs, dim3((int)cdiv64(n * k, 256)), dim3(256), 0, st, (int)n,
+                     (int)k, words, knn.as<int32_t>(), bm.as<uint32_t>());
+  hipLaunchKernelGGL(k_row_counts, dim3((int)cdiv64(n, 256)), dim3(256), 0, st, (int)n, words,
+                     bm.as<uint32_t>(), cnt.as<int32_t>());
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (int)n, cnt.as<int32_t>(),
+                     off.as<int32_t>(), total.as<int64_t>());
+  int64_t E = 0;
+  CC_HIP(hipMemcpyAsync(&E, total.p, 8, hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (E > capacity) {
+    set_error("edge capacity " + std::to_string(capacity) + " < " + std::to_string(E));
+    *n_edges = E;
+    return CC_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_emit_edges, dim3((int)cdiv64(n, 256)), dim3(256), 0, st, (int)n, words,
+                     bm.as<uint32_t>(), off.as<int32_t>(), ei, ej);
+  KN_TRY(d2.alloc(E * 8));
+  if (E > 0) {
+    hipLaunchKernelGGL(k_edge_d2, dim3((int)cdiv64(E, 4)), dim3(256), 0, st, (int)E, (int)p,
+                       Xd.as<double>(), ei, ej, d2.as<double>());
+  }
+  double hphi = phi;
+  if (phi < 0.0 && E > 0) {
+    hipLaunchKernelGGL(k_lower_median, dim3(1), dim3(1024), 0, st, (int)E, d2.as<double>(),
+                       med.as<double>());
+    hipLaunchKernelGGL(k_phi_from_median, dim3(1), dim3(1), 0, st, med.as<double>(), -phi,
+                       phid.as<double>());
+  } else {
+    if (phi < 0.0) hphi = 0.0;
+    CC_HIP(hipMemcpyAsync(phid.p, &hphi, 8, hipMemcpyHostToDevice, st));
+  }
+  if (E > 0) {
+    hipLaunchKernelGGL(k_weights, dim3((int)cdiv64(E, 256)), dim3(256), 0, st, (int)E,
+                       d2.as<double>(), phid.as<double>(), w);
+    if (normalize) hipLaunchKernelGGL(k_normalize, dim3(1), dim3(1024), 0, st, (int)E, w);
+  }
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipMemcpyAsync(&hphi, phid.p, 8, hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  *n_edges = E;
+  if (phi_used) *phi_used = hphi;
+  return CC_OK;
+}
+
+cc_status build_knn_weights(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
+                            const uint8_t *mask, int64_t ldm, int32_t k, double phi,
+                            int32_t normalize, int32_t *ei, int32_t *ej, double *w,
+                            int64_t capacity, int64_t *n_edges, double *phi_used,
+                            hipStream_t stream) {
+  if (n < 2 || p < 1) { set_error("need n >= 2 and p >= 1"); return CC_ERR_INVALID_ARG; }
+  if (n > 16384) { set_error("cc_build_knn_weights supports n <= 16384"); return CC_ERR_INVALID_ARG; }
+  if ((int64_t)n * p > ((int64_t)1 << 31) - 1) { set_error("n * p too large"); return CC_ERR_INVALID_ARG; }
+  if (k < 1 || k >= n) { set_error("need 1 <= k < n"); return CC_ERR_INVALID_ARG; }
+  if (!X || !ei || !ej || !w || !n_edges) { set_error("NULL argument"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype != CC_DTYPE_F32 && x_dtype != CC_DTYPE_F64) { set_error("bad x_dtype"); return CC_ERR_INVALID_ARG; }
+  if (ldx < p || (mask && ldm < p)) { set_error("leading dimension < p"); return CC_ERR_INVALID_ARG; }
+  if (!std::isfinite(phi)) { set_error("phi must be finite"); return CC_ERR_INVALID_ARG; }
+  if (capacity < 0) { set_error("capacity < 0"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype == CC_DTYPE_F32)
+    return knn_impl<float>(n, p, (const float *)X, ldx, mask, ldm, k, phi, normalize, ei, ej, w,
+                           capacity, n_edges, phi_used, stream);
+  return knn_impl<double>(n, p, (const double *)X, ldx, mask, ldm, k, phi, normalize, ei, ej, w,
+                          capacity, n_edges, phi_used, stream);
+}
+
+cc_status standardize_columns(int64_t n, int64_t p, int32_t x_dtype, void *X, int64_t ldx,
+                              const uint8_t *mask, int64_t ldm, hipStream_t st) {
+  if (n < 1 || p < 1) { set_error("need n, p >= 1"); return CC_ERR_INVALID_ARG; }
+  if (!X) { set_error("X is NULL"); return CC_ERR_INVALID_ARG; }
+  if (ldx < p || (mask && ldm < p)) { set_error("leading dimension < p"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype != CC_DTYPE_F32 && x_dtype != CC_DTYPE_F64) { set_error("bad x_dtype"); return CC_ERR_INVALID_ARG; }
+  if ((int64_t)n * p > ((int64_t)1 << 31) - 1) { set_error("n * p too large"); return CC_ERR_INVALID_ARG; }
+  DevBuf mean, sd, bad;
+  KN_TRY(mean.alloc(p * 8));
+  KN_TRY(sd.alloc(p * 8));
+  KN_TRY(bad.alloc(4));
+  CC_HIP(hipMemsetAsync(bad.p, 0, 4, st));
+  const int cb = (int)cdiv64(p, 256), eb = (int)cdiv64(n * p, 256);
+  if (x_dtype == CC_DTYPE_F32) {
+    hipLaunchKernelGGL((k_col_moments<float>), dim3(cb), dim3(256), 0, st, (int)n, (int)p,
+                       (const float *)X, ldx, mask, ldm, mean.as<double>(), sd.as<double>(), bad.as<int>());
+  } else {
+    hipLaunchKernelGGL((k_col_moments<double>), dim3(cb), dim3(256), 0, st, (int)n, (int)p,
+                       (const double *)X, ldx, mask, ldm, mean.as<double>(), sd.as<double>(), bad.as<int>());
+  }
+  int hbad = 0;
+  CC_HIP(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (hbad) { set_error("observed X has non-finite entries"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype == CC_DTYPE_F32)
+    hipLaunchKernelGGL((k_standardize<float>), dim3(eb), dim3(256), 0, st, (int)n, (int)p,
+                       (float *)X, ldx, mask, ldm, mean.as<double>(), sd.as<double>());
+  else
+    hipLaunchKernelGGL((k_standardize<double>), dim3(eb), dim3(256), 0, st, (int)n, (int)p,
+                       (double *)X, ldx, mask, ldm, mean.as<double>(), sd.as<double>());
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipStreamSynchronize(st));
+  return CC_OK;
+}
+
+}  // namespace ccmi

@@ -1,0 +1,1204 @@
+// Proximal-distance MM solver for convex clustering on gfx950 (CDNA4).
+//
+// One MM iteration m (Section "The Proximal Distance Algorithm", the block-
+// descent projection for sparse weights, and Section "Missing Data") runs as
+// three kernels over device-resident state:
+//
+//   k_point   for every point i and feature tile: finish the U update of
+//             iteration m-1, u_i = a'_i + theta (y_i - a'_i) with
+//             theta = d/(d+rho) and y = x on observed entries, u elsewhere
+//             (the same as (d y + rho a)/(d + rho)); then one Jacobi sweep of
+//             the paper's block update
+//               a_i = (u_i + sum_R v_ij - sum_L v_ji + sum_N a'_j)/(1+|N_i|)
+//             with the factored V = diag(s) D A', written in pull form
+//               a_i = a'_i + (u_i - a'_i + sum_j c_ij (a'_j - a'_i))/(1+|N_i|),
+//             c_ij = 1 - s_ij.  The shrink factors s_ij of the V update
+//             (group soft-threshold) are recomputed on the fly from the edge
+//             norms and d of iteration m-1.  Per-block FP64 partial sums feed
+//             d, the objective and the stopping test.
+//   k_edge    per edge and tile: partial ||a_i - a_j||^2 of the new A.
+//   k_edge_reduce  per edge: ||b_e||, the terms of ||V - D A||^2 and of the
+//             penalty; the last block to finish reduces every partial in a
+//             fixed order and advances the iteration (d, objective, stop test).
+//
+// ||V - D A||^2 is assembled as sum_e s_e^2 ||b'_e||^2
+//   - 2 sum_i <h_i, a_i> + sum_e ||b_e||^2, with h_i = sum_j s_ij (a'_i - a'_j)
+// accumulated by k_point in FP64, so the edge pass gathers one row per edge.
+//
+// Pair arithmetic is FP64 on values read from the gather copy of A (FP32 in
+// the F32 and MIXED precisions); every reduction is FP64 and atomic-free
+// except the single last-block counter.  Blocks are mapped to feature tiles
+// tile-major per XCD so that each XCD's L2 holds the rows of the tiles it
+// sweeps.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "ccmi_internal.h"
+
+namespace ccmi {
+
+// ------------------------------------------------------------------ traits
+template <int PREC> struct Traits;
+template <> struct Traits<kF32> {
+  using TS = float; using TG = float; using TX = float;
+  static constexpr bool mirror = false;
+};
+template <> struct Traits<kMixed> {
+  using TS = double; using TG = float; using TX = float;
+  static constexpr bool mirror = true;
+};
+template <> struct Traits<kF64> {
+  using TS = double; using TG = double; using TX = double;
+  static constexpr bool mirror = false;
+};
+
+// ------------------------------------------------------ vector load/store
+template <int VEC> struct VecIO;
+template <> struct VecIO<4> {
+  __device__ static void load(const float *p, double (&o)[4]) {
+    float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+  __device__ static void load(const double *p, double (&o)[4]) {
+    double2 a = *reinterpret_cast<const double2 *>(p);
+    double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  }
+  __device__ static void store(float *p, const double (&v)[4]) {
+    *reinterpret_cast<float4 *>(p) =
+        make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+  }
+  __device__ static void store(double *p, const double (&v)[4]) {
+    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+  }
+  __device__ static void load_mask(const uint8_t *p, bool (&o)[4]) {
+    uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+    o[0] = (v & 0xffu) != 0; o[1] = (v & 0xff00u) != 0;
+    o[2] = (v & 0xff0000u) != 0; o[3] = (v & 0xff000000u) != 0;
+  }
+};
+template <> struct VecIO<2> {
+  __device__ static void load(const float *p, double (&o)[2]) {
+    float2 v = *reinterpret_cast<const float2 *>(p);
+    o[0] = v.x; o[1] = v.y;
+  }
+  __device__ static void load(const double *p, double (&o)[2]) {
+    double2 a = *reinterpret_cast<const double2 *>(p);
+    o[0] = a.x; o[1] = a.y;
+  }
+  __device__ static void store(float *p, const double (&v)[2]) {
+    *reinterpret_cast<float2 *>(p) = make_float2((float)v[0], (float)v[1]);
+  }
+  __device__ static void store(double *p, const double (&v)[2]) {
+    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+  }
+  __device__ static void load_mask(const uint8_t *p, bool (&o)[2]) {
+    uint16_t v = *reinterpret_cast<const uint16_t *>(p);
+    o[0] = (v & 0xffu) != 0; o[1] = (v & 0xff00u) != 0;
+  }
+};
+template <> struct VecIO<1> {
+  __device__ static void load(const float *p, double (&o)[1]) { o[0] = *p; }
+  __device__ static void load(const double *p, double (&o)[1]) { o[0] = *p; }
+  __device__ static void store(float *p, const double (&v)[1]) { *p = (float)v[0]; }
+  __device__ static void store(double *p, const double (&v)[1]) { *p = v[0]; }
+  __device__ static void load_mask(const uint8_t *p, bool (&o)[1]) { o[0] = *p != 0; }
+};
+
+template <typename T> __device__ inline double round_to(double v) { return (double)(T)v; }
+
+__device__ inline double readlane_d(double v, int k) {
+  long long bits = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), k);
+  int hi = __builtin_amdgcn_readlane((int)(bits >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Fixed-order block reduction of NV doubles per thread; result valid in
+// thread 0.  Uses a shared scratch of kWavesPerBlock * NV doubles.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double *scratch) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) scratch[wave * NV + q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double acc = 0.0;
+      for (int w = 0; w < (int)(blockDim.x / kWave); ++w) acc += scratch[w * NV + q];
+      v[q] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Logical block index: physical block b runs on XCD b % 8 (round-robin
+// dispatch); XCD x is given the x-th contiguous eighth of the logical range,
+// so each XCD sweeps a contiguous run of feature tiles.
+__device__ inline int logical_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  return (b % kXcds) * (nb / kXcds) + b / kXcds;
+}
+
+// ---------------------------------------------------------------- params
+struct PointArgs {
+  int n, ld, ntile, nitems, chunk;
+  const void *X;
+  const uint8_t *M;
+  void *U;
+  void *A0, *A1, *G0, *G1;
+  void *Usnap, *Asnap;
+  const int32_t *rowptr, *col, *eid;
+  const double *w;
+  double *s;
+  const double *nb0, *nb1;
+  double *psum;
+  DevScalars *sc;
+};
+
+struct EdgeArgs {
+  int n, ld, ntile, nitems, chunk, init;
+  const void *G0, *G1;
+  const int32_t *rowptr, *uptr, *col, *eid;
+  double *part;
+  DevScalars *sc;
+};
+
+struct ReduceArgs {
+  int E, ntile, nbp, init;
+  const double *part;
+  double *nb0, *nb1;
+  const double *s, *w;
+  double *esum;
+  const double *psum;
+  double *trace;
+  DevScalars *sc;
+};
+
+// ------------------------------------------------------------- k_point
+template <int PREC, int VEC>
+__global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
+  using TS = typename Traits<PREC>::TS;
+  using TG = typename Traits<PREC>::TG;
+  using TX = typename Traits<PREC>::TX;
+  __shared__ double scratch[kWavesPerBlock * kPointSums];
+  DevScalars *sc = a.sc;
+  if (sc->done) return;
+  const int m = sc->m, pa = sc->pa;
+  const double rho = sc->rho, dprev = sc->d_prev;
+  const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
+  const double tau_scale = (m > 0) ? sc->mu * dprev / rho : 0.0;
+  // stop-test window: U snapshots at m = 0, K, 2K, ...; A snapshots at
+  // m = K-1, 2K-1, ... (the start-of-solve A' seeds the first A window)
+  const int K = sc->K;
+  const bool snapU0 = (m == 0), winU = (m > 0) && (m % K == 0);
+  const bool initA = (m == 0) && (K > 1), winA = (m % K) == (K - 1);
+  TS *Us = reinterpret_cast<TS *>(a.Usnap);
+  TS *As = reinterpret_cast<TS *>(a.Asnap);
+  const TS *Ap = reinterpret_cast<const TS *>(pa == 0 ? a.A0 : a.A1);
+  TS *An = reinterpret_cast<TS *>(pa == 0 ? a.A1 : a.A0);
+  const TG *Gp = reinterpret_cast<const TG *>(pa == 0 ? a.G0 : a.G1);
+  TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
+  const double *nbp = pa == 0 ? a.nb0 : a.nb1;
+  const TX *X = reinterpret_cast<const TX *>(a.X);
+  TS *U = reinterpret_cast<TS *>(a.U);
+
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int lb = logical_block();
+  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
+  const int W = kWave * VEC;
+  double ps[kPointSums] = {0, 0, 0, 0, 0, 0};
+
+  for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
+    const int t = item / a.n, i = item - t * a.n;
+    const int f0 = t * W + lane * VEC;
+    const bool active = f0 < a.ld;
+    const size_t row = (size_t)i * a.ld + f0;
+    const int rs = a.rowptr[i], re = a.rowptr[i + 1];
+    const int deg = re - rs;
+
+    double gi[VEC], ap[VEC], up[VEC], x[VEC];
+    bool mk[VEC];
+    double sumg[VEC], sumcg[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) { gi[v] = ap[v] = up[v] = x[v] = 0.0; mk[v] = true; sumg[v] = sumcg[v] = 0.0; }
+    if (active) {
+      VecIO<VEC>::load(Gp + row, gi);
+      VecIO<VEC>::load(Ap + row, ap);
+      VecIO<VEC>::load(U + row, up);
+      VecIO<VEC>::load(X + row, x);
+      if (a.M) VecIO<VEC>::load_mask(a.M + row, mk);
+    }
+    double C = 0.0;
+    for (int base = rs; base < re; base += kWave) {
+      const int cnt = min(kWave, re - base);
+      int jl = 0;
+      double cl = 0.0;
+      if (lane < cnt) {
+        jl = a.col[base + lane];
+        const int e = a.eid[base + lane];
+        if (m > 0) {
+          const double nbv = nbp[e];
+          const double tau = a.w[e] * tau_scale;
+          cl = (nbv > tau) ? tau / nbv : 1.0;   // c = 1 - s, s = max(1 - tau/nb, 0)
+          if (t == 0 && jl > i) a.s[e] = 1.0 - cl;
+        } else {
+          cl = 1.0 - a.s[e];
+        }
+      }
+      int k = 0;
+      for (; k + 4 <= cnt; k += 4) {
+        const int j0 = __builtin_amdgcn_readlane(jl, k);
+        const int j1 = __builtin_amdgcn_readlane(jl, k + 1);
+        const int j2 = __builtin_amdgcn_readlane(jl, k + 2);
+        const int j3 = __builtin_amdgcn_readlane(jl, k + 3);
+        const double c0 = readlane_d(cl, k), c1 = readlane_d(cl, k + 1);
+        const double c2 = readlane_d(cl, k + 2), c3 = readlane_d(cl, k + 3);
+        C += c0; C += c1; C += c2; C += c3;
+        if (active) {
+          double x0[VEC], x1[VEC], x2[VEC], x3[VEC];
+          VecIO<VEC>::load(Gp + (size_t)j0 * a.ld + f0, x0);
+          VecIO<VEC>::load(Gp + (size_t)j1 * a.ld + f0, x1);
+          VecIO<VEC>::load(Gp + (size_t)j2 * a.ld + f0, x2);
+          VecIO<VEC>::load(Gp + (size_t)j3 * a.ld + f0, x3);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            sumg[v] += x0[v]; sumcg[v] = fma(c0, x0[v], sumcg[v]);
+            sumg[v] += x1[v]; sumcg[v] = fma(c1, x1[v], sumcg[v]);
+            sumg[v] += x2[v]; sumcg[v] = fma(c2, x2[v], sumcg[v]);
+            sumg[v] += x3[v]; sumcg[v] = fma(c3, x3[v], sumcg[v]);
+          }
+        }
+      }
+      for (; k < cnt; ++k) {
+        const int j0 = __builtin_amdgcn_readlane(jl, k);
+        const double c0 = readlane_d(cl, k);
+        C += c0;
+        if (active) {
+          double x0[VEC];
+          VecIO<VEC>::load(Gp + (size_t)j0 * a.ld + f0, x0);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) { sumg[v] += x0[v]; sumcg[v] = fma(c0, x0[v], sumcg[v]); }
+        }
+      }
+    }
+    if (active) {
+      const double inv1d = 1.0 / (1.0 + (double)deg);
+      const double S = (double)deg - C;
+      double u[VEC], an[VEC], gn[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        double uu;
+        if (m > 0) {
+          const double y = mk[v] ? x[v] : up[v];
+          uu = ap[v] + theta * (y - ap[v]);
+        } else {
+          uu = up[v];
+        }
+        uu = round_to<TS>(uu);
+        const double jac = sumcg[v] - C * gi[v];                 // sum_j c (a'_j - a'_i)
+        const double h = S * gi[v] - (sumg[v] - sumcg[v]);       // sum_j s (a'_i - a'_j)
+        double anew = ap[v] + (uu - ap[v] + jac) * inv1d;
+        anew = round_to<TS>(anew);
+        const double g = round_to<TG>(anew);
+        u[v] = uu; an[v] = anew; gn[v] = g;
+        const double dua = uu - anew;
+        ps[0] = fma(dua, dua, ps[0]);
+        if (mk[v]) { const double r = x[v] - uu; ps[3] = fma(r, r, ps[3]); }
+        ps[4] = fma(uu, uu, ps[4]);
+        ps[5] = fma(h, g, ps[5]);
+      }
+      VecIO<VEC>::store(U + row, u);
+      VecIO<VEC>::store(An + row, an);
+      if (Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, gn);
+      if (winU) {
+        double us[VEC];
+        VecIO<VEC>::load(Us + row, us);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) { const double du = u[v] - us[v]; ps[2] = fma(du, du, ps[2]); }
+      }
+      if (snapU0 || winU) VecIO<VEC>::store(Us + row, u);
+      if (initA) VecIO<VEC>::store(As + row, ap);
+      if (winA) {
+        double prev[VEC];
+        if (m == 0) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) prev[v] = ap[v];
+        } else {
+          VecIO<VEC>::load(As + row, prev);
+        }
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) { const double da = an[v] - prev[v]; ps[1] = fma(da, da, ps[1]); }
+        VecIO<VEC>::store(As + row, an);
+      }
+    }
+  }
+  block_sum<kPointSums>(ps, scratch);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kPointSums; ++q) a.psum[(size_t)lb * 8 + q] = ps[q];
+  }
+}
+
+// -------------------------------------------------------------- k_edge
+// One wave per (point i, tile); each quarter-wave takes one upper neighbour
+// j > i and sums (a_i - a_j)^2 over the tile, 4 features per lane per pass.
+template <int PREC, int VEC>
+__global__ __launch_bounds__(kBlock) void k_edge(EdgeArgs a) {
+  using TG = typename Traits<PREC>::TG;
+  DevScalars *sc = a.sc;
+  if (!a.init && sc->done) return;
+  const int pa = sc->pa;
+  // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
+  const int buf = a.init ? pa : (pa ^ 1);
+  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int q = lane / 16, l16 = lane % 16;
+  const int lb = logical_block();
+  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
+  const int W = kWave * VEC;
+  for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
+    const int t = item / a.n, i = item - t * a.n;
+    double gi[VEC][4];
+#pragma unroll
+    for (int ps = 0; ps < VEC; ++ps) {
+      const int fo = t * W + ps * 64 + l16 * 4;
+      if (fo < a.ld) VecIO<4>::load(Gc + (size_t)i * a.ld + fo, gi[ps]);
+      else { gi[ps][0] = gi[ps][1] = gi[ps][2] = gi[ps][3] = 0.0; }
+    }
+    const int us = a.uptr[i], re = a.rowptr[i + 1];
+    for (int k = us; k < re; k += 4) {
+      const int kk = k + q;
+      const bool valid = kk < re;
+      int j = i, e = 0;
+      if (valid) { j = a.col[kk]; e = a.eid[kk]; }
+      double acc = 0.0;
+#pragma unroll
+      for (int ps = 0; ps < VEC; ++ps) {
+        const int fo = t * W + ps * 64 + l16 * 4;
+        if (valid && fo < a.ld) {
+          double xj[4];
+          VecIO<4>::load(Gc + (size_t)j * a.ld + fo, xj);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) { const double d = gi[ps][v] - xj[v]; acc = fma(d, d, acc); }
+        }
+      }
+      acc += __shfl_xor(acc, 8, kWave);
+      acc += __shfl_xor(acc, 4, kWave);
+      acc += __shfl_xor(acc, 2, kWave);
+      acc += __shfl_xor(acc, 1, kWave);
+      if (valid && l16 == 0) a.part[(size_t)e * a.ntile + t] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------- k_edge_reduce
+__device__ void finish_iteration(const ReduceArgs &a, double *red) {
+  DevScalars *sc = a.sc;
+  // fixed-order sums of the point partials and of the edge partials
+  double v[kPointSums + kEdgeSums];
+#pragma unroll
+  for (int q = 0; q < kPointSums + kEdgeSums; ++q) v[q] = 0.0;
+  for (int b = threadIdx.x; b < a.nbp; b += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < kPointSums; ++q) v[q] += a.psum[(size_t)b * 8 + q];
+  }
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < kEdgeSums; ++q) v[kPointSums + q] += a.esum[(size_t)b * 4 + q];
+  }
+  block_sum<kPointSums + kEdgeSums>(v, red);
+  if (threadIdx.x != 0) return;
+  const double uA2 = v[0], dAw = v[1], dUw = v[2], loss2 = v[3], u2 = v[4], cross = v[5];
+  const double Cs = v[6], As = v[7], pen = v[8];
+  const double viol = fmax(As - 2.0 * cross + Cs, 0.0);
+  const double d = sqrt(uA2 + viol + sc->eps);
+  const double F = 0.5 * loss2 + sc->mu * pen + sc->rho * d;
+  const int m = sc->m;
+  if (sc->record && a.trace) a.trace[m] = F;
+  if (!isfinite(d) || !isfinite(F)) {
+    sc->status = CC_ERR_NUMERIC; sc->done = 1; sc->iters = m;
+    return;
+  }
+  const int K = sc->K;
+  if (m >= 1) {
+    // iteration m-1 of the MM loop has now finished
+    sc->F_last = sc->F_cur;
+    sc->d_last = sc->d_prev;
+    if (m % K == 0) {
+      const double r = sqrt(dUw + sc->dA_prev) / (double)K;
+      const double unorm = fmax(1.0, sqrt(u2));
+      sc->rel_last = r / unorm;
+      if (sc->thr > 0.0 && m - 1 >= 2 && r <= sc->thr * unorm) {
+        sc->done = 1; sc->converged = 1; sc->iters = m;
+        return;
+      }
+    }
+    if (m >= sc->max_iter) {
+      sc->done = 1; sc->converged = 0; sc->iters = m;
+      return;
+    }
+  }
+  sc->F_cur = F;
+  sc->d_prev = d;
+  if (m % K == K - 1) sc->dA_prev = dAw;
+  sc->pa ^= 1;
+  sc->m = m + 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_edge_reduce(ReduceArgs a) {
+  __shared__ double red[kWavesPerBlock * (kPointSums + kEdgeSums)];
+  __shared__ int is_last;
+  DevScalars *sc = a.sc;
+  if (!a.init && sc->done) return;
+  const int pa = sc->pa;
+  double *nbout = a.init ? (pa == 0 ? a.nb0 : a.nb1) : (pa == 0 ? a.nb1 : a.nb0);
+  const double *nbprev = pa == 0 ? a.nb0 : a.nb1;
+  double t3[kEdgeSums] = {0.0, 0.0, 0.0};
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < a.E; e += gridDim.x * blockDim.x) {
+    double nb2 = 0.0;
+    for (int t = 0; t < a.ntile; ++t) nb2 += a.part[(size_t)e * a.ntile + t];
+    nbout[e] = sqrt(nb2);
+    if (!a.init) {
+      const double sv = a.s[e], np = nbprev[e];
+      t3[0] += nb2;
+      t3[1] += (sv * np) * (sv * np);
+      t3[2] += a.w[e] * sv * np;
+    }
+  }
+  if (a.init) return;
+  block_sum<kEdgeSums>(t3, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kEdgeSums; ++q) a.esum[(size_t)blockIdx.x * 4 + q] = t3[q];
+    __threadfence();
+    const unsigned prev = atomicAdd(&sc->counter, 1u);
+    is_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  finish_iteration(a, red);
+  if (threadIdx.x == 0) sc->counter = 0u;
+}
+
+// --------------------------------------------------------- small kernels
+__global__ void k_set_params(DevScalars *sc, double mu, double rho, double eps,
+                             double thr, int max_iter, int record, int K) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  sc->mu = mu; sc->rho = rho; sc->eps = eps; sc->thr = thr;
+  sc->max_iter = max_iter; sc->record = record; sc->K = K;
+  sc->m = 0; sc->done = 0; sc->converged = 0; sc->status = 0; sc->iters = 0;
+  sc->d_prev = 0.0; sc->dA_prev = 0.0; sc->F_cur = 0.0;
+  sc->F_last = 0.0; sc->d_last = 0.0; sc->rel_last = 0.0;
+  sc->counter = 0u;
+}
+
+__global__ void k_reset_scalars(DevScalars *sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  memset(sc, 0, sizeof(DevScalars));
+}
+
+// Column statistics over observed entries: mean, ||x - mean||^2, and a count
+// of non-finite observed entries.  One thread per column.
+template <typename TI>
+__global__ void k_colstats(int n, int p, const TI *X, int64_t ldx,
+                           const uint8_t *M, int64_t ldm, double *mean,
+                           double *dev2, int *nonfinite) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= p) return;
+  double sum = 0.0;
+  int cnt = 0, bad = 0;
+  for (int i = 0; i < n; ++i) {
+    if (M && M[(size_t)i * ldm + f] == 0) continue;
+    const double x = (double)X[(size_t)i * ldx + f];
+    if (!isfinite(x)) { ++bad; continue; }
+    sum += x; ++cnt;
+  }
+  const double mu = cnt > 0 ? sum / cnt : 0.0;
+  double ss = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (M && M[(size_t)i * ldm + f] == 0) continue;
+    const double x = (double)X[(size_t)i * ldx + f];
+    if (!isfinite(x)) continue;
+    ss += (x - mu) * (x - mu);
+  }
+  mean[f] = mu;
+  dev2[f] = ss;
+  if (bad) atomicAdd(nonfinite, bad);
+}
+
+// Initial state: X-tilde (missing -> observed column mean), U = A = X-tilde,
+// padding columns p..ld-1 zero and observed.
+template <int PREC, typename TI>
+__global__ void k_init_state(int n, int p, int ld, const TI *Xin, int64_t ldx,
+                             const uint8_t *Min, int64_t ldm, const double *mean,
+                             void *Xo, uint8_t *Mo, void *Uo, void *A0, void *G0) {
+  using TS = typename Traits<PREC>::TS;
+  using TG = typename Traits<PREC>::TG;
+  using TX = typename Traits<PREC>::TX;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * ld) return;
+  const int i = (int)(idx / ld), f = (int)(idx % ld);
+  double x = 0.0, xt = 0.0;
+  bool obs = true;
+  if (f < p) {
+    obs = Min ? (Min[(size_t)i * ldm + f] != 0) : true;
+    x = obs ? (double)Xin[(size_t)i * ldx + f] : mean[f];
+    xt = obs ? (double)(TX)x : mean[f];
+  }
+  reinterpret_cast<TX *>(Xo)[idx] = (TX)(obs ? x : xt);
+  if (Mo) Mo[idx] = obs ? 1 : 0;
+  reinterpret_cast<TS *>(Uo)[idx] = (TS)xt;
+  reinterpret_cast<TS *>(A0)[idx] = (TS)xt;
+  if (Traits<PREC>::mirror) reinterpret_cast<TG *>(G0)[idx] = (TG)(TS)xt;
+}
+
+__global__ void k_fill(double *v, int64_t n, double val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = val;
+}
+
+template <typename TS, typename TO>
+__global__ void k_copy_rows(int n, int p, const TS *src, int ld, TO *dst, int64_t ldo) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * p) return;
+  const int i = (int)(idx / p), f = (int)(idx % p);
+  dst[(size_t)i * ldo + f] = (TO)src[(size_t)i * ld + f];
+}
+
+template <int PREC>
+__global__ void k_set_rows(int n, int p, int ld, const double *U, const double *A,
+                           int64_t lds, void *Uo, void *Ao, void *Go) {
+  using TS = typename Traits<PREC>::TS;
+  using TG = typename Traits<PREC>::TG;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * ld) return;
+  const int i = (int)(idx / ld), f = (int)(idx % ld);
+  double u = 0.0, a = 0.0;
+  if (f < p) { u = U[(size_t)i * lds + f]; a = A[(size_t)i * lds + f]; }
+  reinterpret_cast<TS *>(Uo)[idx] = (TS)u;
+  reinterpret_cast<TS *>(Ao)[idx] = (TS)a;
+  if (Traits<PREC>::mirror) reinterpret_cast<TG *>(Go)[idx] = (TG)(TS)a;
+}
+
+__global__ void k_fused_flags(int E, const double *s, uint8_t *out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E) out[e] = (s[e] == 0.0) ? 1 : 0;
+}
+
+// Connected components of the kept edges (keep[e] != 0, or s[e] == 0 when
+// keep is null), labelled by the smallest vertex index: min-label hooking
+// with pointer jumping, one workgroup, at most n + 2 rounds.
+__global__ __launch_bounds__(1024) void k_components(int n, int E, const int32_t *ei,
+                                                     const int32_t *ej, const uint8_t *keep,
+                                                     const double *s, int32_t *lab, int32_t *ncl) {
+  __shared__ int changed;
+  __shared__ int cnt_s[1024 / kWave];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lab[i] = i;
+  __syncthreads();
+  for (int round = 0; round < n + 2; ++round) {
+    if (threadIdx.x == 0) changed = 0;
+    __syncthreads();
+    int local = 0;
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+      const bool fused = keep ? (keep[e] != 0) : (s[e] == 0.0);
+      if (!fused) continue;
+      const int a = ei[e], b = ej[e];
+      const int la = __hip_atomic_load(&lab[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int lbv = __hip_atomic_load(&lab[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (la != lbv) {
+        const int lo = min(la, lbv), hi = max(la, lbv);
+        atomicMin(&lab[a], lo);
+        atomicMin(&lab[b], lo);
+        atomicMin(&lab[hi], lo);
+        local = 1;
+      }
+    }
+    if (local) changed = 1;
+    __syncthreads();
+    // pointer jumping
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      int l = __hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int ll = __hip_atomic_load(&lab[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (ll < l) {
+        l = ll;
+        ll = __hip_atomic_load(&lab[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      atomicMin(&lab[i], l);
+    }
+    __syncthreads();
+    const int ch = changed;
+    __syncthreads();
+    if (!ch) break;
+  }
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    c += (__hip_atomic_load(&lab[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == i) ? 1 : 0;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+  if (threadIdx.x % kWave == 0) cnt_s[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) tot += cnt_s[w];
+    *ncl = tot;
+  }
+}
+
+// ====================================================================== host
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static size_t ts_size(int prec) { return prec == kF32 ? 4 : 8; }
+static size_t tx_size(int prec) { return prec == kF64 ? 8 : 4; }
+static size_t tg_size(int prec) { return prec == kF64 ? 8 : 4; }
+
+struct Launch {
+  int blocks, chunk, nitems;
+};
+
+// Grid for a sweep over nitems wave-items: at most kMaxBlocks blocks, a
+// multiple of the XCD count, each block owning a contiguous chunk.
+static Launch sweep_grid(int64_t nitems) {
+  Launch L;
+  L.nitems = (int)nitems;
+  int64_t want = cdiv(std::max<int64_t>(nitems, 1), kWavesPerBlock);
+  int64_t blocks = std::min<int64_t>(want, kMaxBlocks);
+  blocks = cdiv(blocks, kXcds) * kXcds;
+  L.blocks = (int)blocks;
+  L.chunk = (int)cdiv(std::max<int64_t>(nitems, 1), blocks);
+  return L;
+}
+
+// Event set for a sampled iteration (cc_profile), or null.
+static hipEvent_t *prof_slot(Problem *P) {
+  if (P->prof_every <= 0) return nullptr;
+  const bool sample = (P->prof_iter++ % P->prof_every) == 0;
+  if (!sample) return nullptr;
+  const size_t need = 4 * (P->prof_used + 1);
+  while (P->prof_events.size() < need) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    P->prof_events.push_back(ev);
+  }
+  return &P->prof_events[4 * P->prof_used++];
+}
+
+template <int PREC, int VEC>
+static void launch_iteration_t(Problem *P) {
+  hipEvent_t *ev = prof_slot(P);
+  if (ev) (void)hipEventRecord(ev[0], P->stream);
+  const Launch Lp = sweep_grid(P->n * P->ntile);
+  PointArgs pa{(int)P->n, (int)P->ld, P->ntile, Lp.nitems, Lp.chunk,
+               P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
+               P->rowptr, P->col, P->eid, P->w, P->s, P->nb[0], P->nb[1],
+               P->psum, P->sc};
+  hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kBlock), 0, P->stream, pa);
+  if (ev) (void)hipEventRecord(ev[1], P->stream);
+  const Launch Le = Lp;
+  EdgeArgs ea{(int)P->n, (int)P->ld, P->ntile, Le.nitems, Le.chunk, 0,
+              P->G[0], P->G[1], P->rowptr, P->uptr, P->col, P->eid, P->part, P->sc};
+  hipLaunchKernelGGL((k_edge<PREC, VEC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea);
+  if (ev) (void)hipEventRecord(ev[2], P->stream);
+  const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
+  ReduceArgs ra{(int)P->E, P->ntile, Lp.blocks, 0, P->part, P->nb[0], P->nb[1],
+                P->s, P->w, P->esum, P->psum, P->trace, P->sc};
+  hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
+  if (ev) (void)hipEventRecord(ev[3], P->stream);
+}
+
+cc_status profile(Problem *P, int32_t sample_every) {
+  CC_HIP(hipStreamSynchronize(P->stream));
+  P->prof_every = sample_every > 0 ? sample_every : 0;
+  P->prof_iter = 0;
+  P->prof_used = 0;
+  for (int q = 0; q < 3; ++q) { P->prof_ms[q] = 0.0; P->prof_n[q] = 0; }
+  return CC_OK;
+}
+
+// Fold the durations of every recorded event set into the statistics.  The
+// caller has synchronised the stream, so every event is complete.
+cc_status harvest_profile(Problem *P) {
+  for (size_t k = 0; k < P->prof_used; ++k) {
+    hipEvent_t *ev = &P->prof_events[4 * k];
+    for (int q = 0; q < 3; ++q) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[q], ev[q + 1]) == hipSuccess) {
+        P->prof_ms[q] += ms;
+        P->prof_n[q] += 1;
+      }
+    }
+  }
+  P->prof_used = 0;
+  return CC_OK;
+}
+
+template <int PREC, int VEC>
+static void launch_edge_init_t(Problem *P) {
+  const Launch Le = sweep_grid(P->n * P->ntile);
+  EdgeArgs ea{(int)P->n, (int)P->ld, P->ntile, Le.nitems, Le.chunk, 1,
+              P->G[0], P->G[1], P->rowptr, P->uptr, P->col, P->eid, P->part, P->sc};
+  hipLaunchKernelGGL((k_edge<PREC, VEC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea);
+  const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
+  ReduceArgs ra{(int)P->E, P->ntile, Le.blocks, 1, P->part, P->nb[0], P->nb[1],
+                P->s, P->w, P->esum, P->psum, P->trace, P->sc};
+  hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
+}
+
+template <int PREC>
+static void dispatch_vec(Problem *P, bool init) {
+  switch (P->vec) {
+    case 1: init ? launch_edge_init_t<PREC, 1>(P) : launch_iteration_t<PREC, 1>(P); break;
+    case 2: init ? launch_edge_init_t<PREC, 2>(P) : launch_iteration_t<PREC, 2>(P); break;
+    default: init ? launch_edge_init_t<PREC, 4>(P) : launch_iteration_t<PREC, 4>(P); break;
+  }
+}
+
+static void launch_iteration(Problem *P) {
+  if (P->precision == kF32) dispatch_vec<kF32>(P, false);
+  else if (P->precision == kF64) dispatch_vec<kF64>(P, false);
+  else dispatch_vec<kMixed>(P, false);
+}
+
+static void launch_edge_init(Problem *P) {
+  if (P->precision == kF32) dispatch_vec<kF32>(P, true);
+  else if (P->precision == kF64) dispatch_vec<kF64>(P, true);
+  else dispatch_vec<kMixed>(P, true);
+}
+
+void problem_free(Problem *P) {
+  if (!P) return;
+  void *bufs[] = {P->X, P->M, P->U, P->A[0], P->A[1], P->Usnap, P->Asnap, P->rowptr, P->col, P->eid, P->uptr,
+                  P->ei, P->ej, P->w, P->s, P->nb[0], P->nb[1], P->part, P->psum,
+                  P->esum, P->trace, P->sc, P->ncl_dev};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (Traits<kMixed>::mirror && P->precision == kMixed) {
+    if (P->G[0]) (void)hipFree(P->G[0]);
+    if (P->G[1]) (void)hipFree(P->G[1]);
+  }
+  for (hipEvent_t ev : P->prof_events) (void)hipEventDestroy(ev);
+  if (P->sc_host) (void)hipHostFree(P->sc_host);
+  if (P->flag_host) (void)hipHostFree(P->flag_host);
+  delete P;
+}
+
+static cc_status dmalloc(void **p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    set_error(std::string("hipMalloc of ") + std::to_string(bytes) + " bytes failed: " +
+              hipGetErrorString(e));
+    return CC_ERR_OUT_OF_MEMORY;
+  }
+  return CC_OK;
+}
+
+#define CC_TRY(x)                       \
+  do {                                  \
+    cc_status _s = (x);                 \
+    if (_s != CC_OK) return _s;         \
+  } while (0)
+
+static void choose_tiles(Problem *P) {
+  // tile width 64*vec features; wider tiles for wide data
+  const char *env = getenv("CCMI_VEC");
+  int vec = 0;
+  if (env) vec = atoi(env);
+  if (vec != 1 && vec != 2 && vec != 4) vec = P->p > 2048 ? 4 : (P->p > 96 ? 2 : 1);
+  P->vec = vec;
+  P->tile_w = kWave * vec;
+  P->ntile = (int)cdiv(P->ld, P->tile_w);
+}
+
+cc_status reset_state(Problem *P);
+
+cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
+                         int64_t ldx, const uint8_t *mask, int64_t ldm,
+                         int64_t n_edges, const int32_t *ei, const int32_t *ej,
+                         const double *w, int32_t precision, hipStream_t stream,
+                         Problem **out) {
+  if (!out) { set_error("out is NULL"); return CC_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (n < 1 || p < 1) { set_error("need n >= 1 and p >= 1"); return CC_ERR_INVALID_ARG; }
+  if (n > (int64_t)1 << 30 || p > (int64_t)1 << 30) { set_error("n or p too large"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype != CC_DTYPE_F32 && x_dtype != CC_DTYPE_F64) { set_error("x_dtype must be CC_DTYPE_F32 or CC_DTYPE_F64"); return CC_ERR_INVALID_ARG; }
+  if (!X) { set_error("X is NULL"); return CC_ERR_INVALID_ARG; }
+  if (ldx < p) { set_error("ldx < p"); return CC_ERR_INVALID_ARG; }
+  if (mask && ldm < p) { set_error("ldm < p"); return CC_ERR_INVALID_ARG; }
+  if (n_edges < 0) { set_error("n_edges < 0"); return CC_ERR_INVALID_ARG; }
+  if (n_edges > 0 && (!ei || !ej || !w)) { set_error("edge arrays are NULL"); return CC_ERR_INVALID_ARG; }
+  if (precision != kF32 && precision != kMixed && precision != kF64) { set_error("unknown precision"); return CC_ERR_INVALID_ARG; }
+  if ((int64_t)n * ((p + 3) / 4 * 4) > ((int64_t)1 << 31) - 1) { set_error("n * p exceeds 2^31"); return CC_ERR_INVALID_ARG; }
+
+  // ---- validate edges and weights on the host ----
+  std::vector<int32_t> hi(n_edges), hj(n_edges);
+  std::vector<double> hw(n_edges);
+  if (n_edges > 0) {
+    CC_HIP(hipMemcpyAsync(hi.data(), ei, n_edges * 4, hipMemcpyDeviceToHost, stream));
+    CC_HIP(hipMemcpyAsync(hj.data(), ej, n_edges * 4, hipMemcpyDeviceToHost, stream));
+    CC_HIP(hipMemcpyAsync(hw.data(), w, n_edges * 8, hipMemcpyDeviceToHost, stream));
+    CC_HIP(hipStreamSynchronize(stream));
+  }
+  std::vector<int64_t> keys(n_edges);
+  for (int64_t e = 0; e < n_edges; ++e) {
+    if (hi[e] < 0 || hj[e] >= n || hi[e] >= hj[e]) {
+      set_error("edge " + std::to_string(e) + " invalid: need 0 <= ei < ej < n");
+      return CC_ERR_INVALID_ARG;
+    }
+    if (!std::isfinite(hw[e]) || !(hw[e] > 0.0)) {
+      set_error("weight " + std::to_string(e) + " must be finite and > 0");
+      return CC_ERR_INVALID_ARG;
+    }
+    keys[e] = (int64_t)hi[e] * n + hj[e];
+  }
+  {
+    std::vector<int64_t> sk(keys);
+    std::sort(sk.begin(), sk.end());
+    for (size_t k = 1; k < sk.size(); ++k)
+      if (sk[k] == sk[k - 1]) { set_error("duplicate edge"); return CC_ERR_INVALID_ARG; }
+  }
+
+  Problem *P = new (std::nothrow) Problem();
+  if (!P) { set_error("host allocation failed"); return CC_ERR_OUT_OF_MEMORY; }
+  P->n = n; P->p = p; P->E = n_edges; P->ld = (p + 3) / 4 * 4;
+  P->precision = precision; P->stream = stream; P->has_mask = mask != nullptr;
+  choose_tiles(P);
+  struct Guard { Problem *&P; bool ok = false; ~Guard() { if (!ok) problem_free(P); } } guard{P};
+
+  const size_t nl = (size_t)n * P->ld;
+  CC_TRY(dmalloc(&P->X, nl * tx_size(precision)));
+  if (mask) CC_TRY(dmalloc((void **)&P->M, nl));
+  CC_TRY(dmalloc(&P->U, nl * ts_size(precision)));
+  CC_TRY(dmalloc(&P->A[0], nl * ts_size(precision)));
+  CC_TRY(dmalloc(&P->A[1], nl * ts_size(precision)));
+  CC_TRY(dmalloc(&P->Usnap, nl * ts_size(precision)));
+  CC_TRY(dmalloc(&P->Asnap, nl * ts_size(precision)));
+  if (precision == kMixed) {
+    CC_TRY(dmalloc(&P->G[0], nl * tg_size(precision)));
+    CC_TRY(dmalloc(&P->G[1], nl * tg_size(precision)));
+  } else {
+    P->G[0] = P->A[0]; P->G[1] = P->A[1];
+  }
+  const int64_t E = n_edges;
+  CC_TRY(dmalloc((void **)&P->rowptr, (n + 1) * 4));
+  CC_TRY(dmalloc((void **)&P->uptr, n * 4));
+  CC_TRY(dmalloc((void **)&P->col, 2 * E * 4));
+  CC_TRY(dmalloc((void **)&P->eid, 2 * E * 4));
+  CC_TRY(dmalloc((void **)&P->ei, E * 4));
+  CC_TRY(dmalloc((void **)&P->ej, E * 4));
+  CC_TRY(dmalloc((void **)&P->w, E * 8));
+  CC_TRY(dmalloc((void **)&P->s, E * 8));
+  CC_TRY(dmalloc((void **)&P->nb[0], E * 8));
+  CC_TRY(dmalloc((void **)&P->nb[1], E * 8));
+  CC_TRY(dmalloc((void **)&P->part, E * P->ntile * 8));
+  CC_TRY(dmalloc((void **)&P->psum, kMaxBlocks * 8 * 8));
+  CC_TRY(dmalloc((void **)&P->esum, kMaxBlocks * 4 * 8));
+  CC_TRY(dmalloc((void **)&P->sc, sizeof(DevScalars)));
+  CC_TRY(dmalloc((void **)&P->ncl_dev, 4));
+  CC_HIP(hipHostMalloc((void **)&P->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+  CC_HIP(hipHostMalloc((void **)&P->flag_host, 64, hipHostMallocDefault));
+
+  // ---- symmetric CSR with sorted columns ----
+  std::vector<int32_t> deg(n + 1, 0);
+  for (int64_t e = 0; e < E; ++e) { deg[hi[e]]++; deg[hj[e]]++; }
+  std::vector<int32_t> rp(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + deg[i];
+  std::vector<std::pair<int32_t, int32_t>> ent(2 * E);
+  {
+    std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
+    for (int64_t e = 0; e < E; ++e) {
+      ent[fill[hi[e]]++] = {hj[e], (int32_t)e};
+      ent[fill[hj[e]]++] = {hi[e], (int32_t)e};
+    }
+  }
+  std::vector<int32_t> hcol(2 * E), heid(2 * E), hup(n);
+  int64_t maxdeg = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    std::sort(ent.begin() + rp[i], ent.begin() + rp[i + 1]);
+    int32_t up = rp[i + 1];
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      hcol[k] = ent[k].first; heid[k] = ent[k].second;
+      if (up == rp[i + 1] && ent[k].first > i) up = k;
+    }
+    hup[i] = up;
+    maxdeg = std::max<int64_t>(maxdeg, rp[i + 1] - rp[i]);
+  }
+  P->max_deg = maxdeg;
+  CC_HIP(hipMemcpyAsync(P->rowptr, rp.data(), (n + 1) * 4, hipMemcpyHostToDevice, stream));
+  CC_HIP(hipMemcpyAsync(P->uptr, hup.data(), n * 4, hipMemcpyHostToDevice, stream));
+  if (E > 0) {
+    CC_HIP(hipMemcpyAsync(P->col, hcol.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
+    CC_HIP(hipMemcpyAsync(P->eid, heid.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
+    CC_HIP(hipMemcpyAsync(P->ei, hi.data(), E * 4, hipMemcpyHostToDevice, stream));
+    CC_HIP(hipMemcpyAsync(P->ej, hj.data(), E * 4, hipMemcpyHostToDevice, stream));
+    CC_HIP(hipMemcpyAsync(P->w, hw.data(), E * 8, hipMemcpyHostToDevice, stream));
+  }
+  double w2 = 0.0;
+  for (int64_t e = 0; e < E; ++e) w2 += hw[e] * hw[e];
+  P->w2 = w2;
+
+  // ---- column statistics and the initial state ----
+  double *mean = nullptr, *dev2 = nullptr;
+  int *bad = nullptr;
+  CC_TRY(dmalloc((void **)&mean, p * 8));
+  struct Tmp { void *a, *b, *c; ~Tmp() { if (a) (void)hipFree(a); if (b) (void)hipFree(b); if (c) (void)hipFree(c); } } tmp{mean, nullptr, nullptr};
+  CC_TRY(dmalloc((void **)&dev2, p * 8));
+  tmp.b = dev2;
+  CC_TRY(dmalloc((void **)&bad, 4));
+  tmp.c = bad;
+  CC_HIP(hipMemsetAsync(bad, 0, 4, stream));
+  const int cb = (int)cdiv(p, 256);
+  if (x_dtype == CC_DTYPE_F32)
+    hipLaunchKernelGGL((k_colstats<float>), dim3(cb), dim3(256), 0, stream, (int)n, (int)p,
+                       (const float *)X, ldx, mask, ldm, mean, dev2, bad);
+  else
+    hipLaunchKernelGGL((k_colstats<double>), dim3(cb), dim3(256), 0, stream, (int)n, (int)p,
+                       (const double *)X, ldx, mask, ldm, mean, dev2, bad);
+  CC_HIP(hipGetLastError());
+  std::vector<double> hdev2(p);
+  int hbad = 0;
+  CC_HIP(hipMemcpyAsync(hdev2.data(), dev2, p * 8, hipMemcpyDeviceToHost, stream));
+  CC_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, stream));
+  CC_HIP(hipStreamSynchronize(stream));
+  if (hbad) { set_error("observed X has non-finite entries"); return CC_ERR_INVALID_ARG; }
+  P->dev2 = std::accumulate(hdev2.begin(), hdev2.end(), 0.0);
+
+  const int ib = (int)cdiv(nl, 256);
+#define CC_INIT(PR, TI)                                                                    \
+  hipLaunchKernelGGL((k_init_state<PR, TI>), dim3(ib), dim3(256), 0, stream, (int)n, (int)p, \
+                     (int)P->ld, (const TI *)X, ldx, mask, ldm, mean, P->X, P->M, P->U,     \
+                     P->A[0], P->G[0])
+  if (x_dtype == CC_DTYPE_F32) {
+    if (precision == kF32) CC_INIT(kF32, float);
+    else if (precision == kF64) CC_INIT(kF64, float);
+    else CC_INIT(kMixed, float);
+  } else {
+    if (precision == kF32) CC_INIT(kF32, double);
+    else if (precision == kF64) CC_INIT(kF64, double);
+    else CC_INIT(kMixed, double);
+  }
+#undef CC_INIT
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipStreamSynchronize(stream));
+  CC_TRY(reset_state(P));
+  guard.ok = true;
+  *out = P;
+  return CC_OK;
+}
+
+// Back to the initial state U = A' = X-tilde, s = 1 (stored in buffer 0).
+cc_status reset_state(Problem *P) {
+  const size_t nl = (size_t)P->n * P->ld;
+  const size_t bytes = nl * ts_size(P->precision);
+  // U and A[0] are rebuilt from the stored X-tilde copy
+  if (P->precision == kF64) {
+    CC_HIP(hipMemcpyAsync(P->U, P->X, bytes, hipMemcpyDeviceToDevice, P->stream));
+    CC_HIP(hipMemcpyAsync(P->A[0], P->X, bytes, hipMemcpyDeviceToDevice, P->stream));
+  } else if (P->precision == kF32) {
+    CC_HIP(hipMemcpyAsync(P->U, P->X, bytes, hipMemcpyDeviceToDevice, P->stream));
+    CC_HIP(hipMemcpyAsync(P->A[0], P->X, bytes, hipMemcpyDeviceToDevice, P->stream));
+  } else {
+    const int b = (int)cdiv(nl, 256);
+    hipLaunchKernelGGL((k_copy_rows<float, double>), dim3(b), dim3(256), 0, P->stream,
+                       (int)P->n, (int)P->ld, (const float *)P->X, (int)P->ld, (double *)P->U,
+                       (int64_t)P->ld);
+    hipLaunchKernelGGL((k_copy_rows<float, double>), dim3(b), dim3(256), 0, P->stream,
+                       (int)P->n, (int)P->ld, (const float *)P->X, (int)P->ld,
+                       (double *)P->A[0], (int64_t)P->ld);
+    CC_HIP(hipMemcpyAsync(P->G[0], P->X, nl * 4, hipMemcpyDeviceToDevice, P->stream));
+  }
+  if (P->E > 0) {
+    hipLaunchKernelGGL(k_fill, dim3((int)cdiv(P->E, 256)), dim3(256), 0, P->stream, P->s,
+                       P->E, 1.0);
+  }
+  hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, P->stream, P->sc);
+  CC_HIP(hipGetLastError());
+  launch_edge_init(P);
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipStreamSynchronize(P->stream));
+  P->state_valid = true;
+  return CC_OK;
+}
+
+static cc_status read_scalars(Problem *P) {
+  CC_HIP(hipMemcpyAsync(P->sc_host, P->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, P->stream));
+  CC_HIP(hipStreamSynchronize(P->stream));
+  return CC_OK;
+}
+
+cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info *info) {
+  if (!(gamma >= 0.0) || !std::isfinite(gamma)) { set_error("gamma must be finite and >= 0"); return CC_ERR_INVALID_ARG; }
+  if (o.max_iter < 1) { set_error("max_iter must be >= 1"); return CC_ERR_INVALID_ARG; }
+  if (o.test_every < 1) { set_error("test_every must be >= 1"); return CC_ERR_INVALID_ARG; }
+  if (!(o.tol >= 0.0)) { set_error("tol must be >= 0"); return CC_ERR_INVALID_ARG; }
+  if (!(o.eta > 0.0) && !(o.eps > 0.0)) { set_error("need eta > 0 or eps > 0"); return CC_ERR_INVALID_ARG; }
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!o.warm_start || !P->state_valid) CC_TRY(reset_state(P));
+  double rho = o.rho > 0 ? o.rho : 2.0 * std::sqrt(P->dev2 + gamma * gamma * P->w2);
+  if (!(rho > 0.0)) rho = 1.0;
+  const double eps = o.eps > 0 ? o.eps : (o.eta * rho) * (o.eta * rho);
+  const double eta = std::sqrt(eps) / rho;
+  const double thr = o.tol > 0 ? o.tol * eta : 0.0;
+  if (o.record_objective) {
+    const int64_t need = (int64_t)o.max_iter + 2;
+    if (P->trace_cap < need) {
+      if (P->trace) (void)hipFree(P->trace);
+      P->trace = nullptr;
+      P->trace_cap = 0;
+      CC_TRY(dmalloc((void **)&P->trace, need * 8));
+      P->trace_cap = need;
+    }
+  }
+  const int record = o.record_objective ? 1 : 0;
+  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, P->stream, P->sc, gamma, rho, eps, thr,
+                     o.max_iter, record, o.test_every);
+  CC_HIP(hipGetLastError());
+  const int check = std::max(1, o.check_every);
+  for (int64_t it = 0; it <= (int64_t)o.max_iter; ++it) {
+    launch_iteration(P);
+    if ((it + 1) % check == 0 || it == (int64_t)o.max_iter) {
+      CC_HIP(hipGetLastError());
+      CC_HIP(hipMemcpyAsync(P->flag_host, &P->sc->done, 4, hipMemcpyDeviceToHost, P->stream));
+      CC_HIP(hipStreamSynchronize(P->stream));
+      if (P->prof_used) harvest_profile(P);
+      if (P->flag_host[0]) break;
+    }
+  }
+  CC_TRY(read_scalars(P));
+  const DevScalars &h = *P->sc_host;
+  P->trace_count = record ? h.iters : 0;
+  cc_status st = h.status == 0 ? CC_OK : (cc_status)h.status;
+  if (!h.done) { set_error("solver did not finish"); st = CC_ERR_STATE; }
+  if (st == CC_ERR_NUMERIC) {
+    set_error("d or the objective became non-finite");
+    P->state_valid = false;
+  }
+  if (info) {
+    info->iters = h.iters;
+    info->converged = h.converged;
+    info->status = st;
+    info->gamma = gamma;
+    info->objective = h.F_last;
+    info->d = h.d_last;
+    info->rel_change = h.rel_last;
+    info->rho = rho;
+    info->eps = eps;
+    info->n_clusters = 0;
+    if (st == CC_OK) {
+      int32_t ncl = 0;
+      // labels of the final state into scratch space reused from part
+      int32_t *lab = nullptr;
+      CC_TRY(dmalloc((void **)&lab, P->n * 4));
+      cc_status ls = write_labels(P, lab, &ncl);
+      (void)hipFree(lab);
+      if (ls != CC_OK) return ls;
+      info->n_clusters = ncl;
+    }
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return st;
+}
+
+cc_status components(int64_t n, int64_t E, const int32_t *ei, const int32_t *ej,
+                     const uint8_t *keep, const double *s, int32_t *labels,
+                     int32_t *ncl_dev, hipStream_t stream) {
+  hipLaunchKernelGGL(k_components, dim3(1), dim3(1024), 0, stream, (int)n, (int)E, ei, ej, keep,
+                     s, labels, ncl_dev);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+cc_status write_labels(Problem *P, int32_t *labels, int32_t *ncl_host) {
+  CC_TRY(components(P->n, P->E, P->ei, P->ej, nullptr, P->s, labels, P->ncl_dev, P->stream));
+  if (ncl_host) {
+    CC_HIP(hipMemcpyAsync(P->flag_host, P->ncl_dev, 4, hipMemcpyDeviceToHost, P->stream));
+    CC_HIP(hipStreamSynchronize(P->stream));
+    *ncl_host = P->flag_host[0];
+  }
+  return CC_OK;
+}
+
+cc_status copy_U(Problem *P, int32_t out_dtype, void *dst, int64_t ldu) {
+  const size_t np = (size_t)P->n * P->p;
+  const int b = (int)cdiv(np, 256);
+  if (P->precision == kF32) {
+    if (out_dtype == CC_DTYPE_F32)
+      hipLaunchKernelGGL((k_copy_rows<float, float>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const float *)P->U, (int)P->ld, (float *)dst, ldu);
+    else
+      hipLaunchKernelGGL((k_copy_rows<float, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const float *)P->U, (int)P->ld, (double *)dst, ldu);
+  } else {
+    if (out_dtype == CC_DTYPE_F32)
+      hipLaunchKernelGGL((k_copy_rows<double, float>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const double *)P->U, (int)P->ld, (float *)dst, ldu);
+    else
+      hipLaunchKernelGGL((k_copy_rows<double, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const double *)P->U, (int)P->ld, (double *)dst, ldu);
+  }
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+cc_status get_fused(Problem *P, uint8_t *fused) {
+  if (P->E == 0) return CC_OK;
+  hipLaunchKernelGGL(k_fused_flags, dim3((int)cdiv(P->E, 256)), dim3(256), 0, P->stream,
+                     (int)P->E, P->s, fused);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+cc_status set_state(Problem *P, const double *U, const double *A, int64_t ld, const double *s) {
+  // the state goes to buffer 0 (pa = 0 after the scalar reset)
+  const size_t nl = (size_t)P->n * P->ld;
+  const int b = (int)cdiv(nl, 256);
+  if (P->precision == kF32)
+    hipLaunchKernelGGL((k_set_rows<kF32>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (int)P->ld, U, A, ld, P->U, P->A[0], P->G[0]);
+  else if (P->precision == kF64)
+    hipLaunchKernelGGL((k_set_rows<kF64>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (int)P->ld, U, A, ld, P->U, P->A[0], P->G[0]);
+  else
+    hipLaunchKernelGGL((k_set_rows<kMixed>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (int)P->ld, U, A, ld, P->U, P->A[0], P->G[0]);
+  if (P->E > 0) CC_HIP(hipMemcpyAsync(P->s, s, P->E * 8, hipMemcpyDeviceToDevice, P->stream));
+  hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, P->stream, P->sc);
+  CC_HIP(hipGetLastError());
+  launch_edge_init(P);
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipStreamSynchronize(P->stream));
+  P->state_valid = true;
+  return CC_OK;
+}
+
+cc_status get_state(Problem *P, double *U, double *A, int64_t ld, double *s) {
+  CC_TRY(read_scalars(P));
+  const int pa = P->sc_host->pa;
+  const size_t np = (size_t)P->n * P->p;
+  const int b = (int)cdiv(np, 256);
+  if (P->precision == kF32) {
+    hipLaunchKernelGGL((k_copy_rows<float, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const float *)P->U, (int)P->ld, U, ld);
+    hipLaunchKernelGGL((k_copy_rows<float, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const float *)P->A[pa], (int)P->ld, A, ld);
+  } else {
+    hipLaunchKernelGGL((k_copy_rows<double, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const double *)P->U, (int)P->ld, U, ld);
+    hipLaunchKernelGGL((k_copy_rows<double, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const double *)P->A[pa], (int)P->ld, A, ld);
+  }
+  if (P->E > 0) CC_HIP(hipMemcpyAsync(s, P->s, P->E * 8, hipMemcpyDeviceToDevice, P->stream));
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+}  // namespace ccmi

@@ -1,0 +1,215 @@
+"""GPU parity of the MM solver (libccmi through the C ABI) against the FP64
+oracle, on the same seeded inputs.
+
+Tolerances (stated per test): FP64 state tracks the oracle's Jacobi-1
+trajectory to rounding; the mixed precision (FP64 point state, FP32 pair
+sweep) stays within max|dU|/max|U| <= 1e-5 of the oracle's fixed point with
+identical fusion partitions; the all-FP32 state stalls up to ~1e-4 away.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mm
+from tests._gpu import (as_f32_values, oracle_jacobi, plain_problem, reduced_expression,
+                        rel_max, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cc():
+    import paper_1409_2065_amd as P
+    P.load()
+    assert torch.cuda.is_available()
+    return P
+
+
+def _gpu(cc, X, mask, edges, w, precision):
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    Xt, m, e, wt = to_dev(X, mask, edges, w, dtype)
+    return cc.Problem(Xt, m, e, wt, precision=precision)
+
+
+# ------------------------------------------------------- trajectory parity
+@pytest.mark.parametrize("iters", [1, 2, 3, 7, 60])
+def test_fixed_iterations_f64_match_oracle_trajectory(cc, iters):
+    X, M, E, w = plain_problem()
+    prob = oracle_jacobi(X, M, E, w)
+    st, info = prob.solve(10.0, mm.Opts(tol=0, max_iter=iters, proj="jacobi:1", record=True))
+    with _gpu(cc, X, M, E, w, "f64") as g:
+        gi = g.solve(10.0, tol=0.0, max_iter=iters, record_objective=1)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+        F = g.trace()
+    assert gi["iters"] == iters and gi["converged"] == 0
+    assert rel_max(U, st.U) < 1e-11
+    assert rel_max(A, st.A) < 1e-11
+    assert np.abs(s - st.s).max() < 1e-9
+    assert np.array_equal(s == 0, st.s == 0)
+    assert np.allclose(F, info.trace_F, rtol=1e-10, atol=0)
+    assert gi["d"] == pytest.approx(info.d, rel=1e-10)
+    assert gi["objective"] == pytest.approx(info.objective, rel=1e-10)
+
+
+@pytest.mark.parametrize("precision,tol", [("mixed", 2e-6), ("f32", 2e-5)])
+def test_fixed_iterations_reduced_precision(cc, precision, tol):
+    X, M, E, w, gam = reduced_expression()
+    prob = oracle_jacobi(X, M, E, w)
+    st, _ = prob.solve(3.0, mm.Opts(tol=0, max_iter=200, proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, precision) as g:
+        g.solve(3.0, tol=0.0, max_iter=200)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    assert rel_max(U, st.U) < tol
+    assert rel_max(A, st.A) < tol
+
+
+# ------------------------------------------------------ converged parity
+def test_plain_config_f64_gamma_1(cc):
+    """Plain workload (n=200, p=10, k=10, phi=0.5, gamma=1), FP64."""
+    X, M, E, w = plain_problem()
+    st, info = oracle_jacobi(X, M, E, w).solve(1.0, mm.Opts(proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, "f64") as g:
+        gi = g.solve(1.0)
+        U = g.U(torch.float64).cpu().numpy()
+        lab, ncl = g.labels()
+    assert gi["converged"] == 1 and info.converged
+    assert abs(gi["iters"] - info.iters) <= mm.DEFAULT_TEST_EVERY
+    assert rel_max(U, st.U) < 1e-8
+    assert np.array_equal(lab.cpu().numpy(), info.labels)
+    assert ncl == info.n_clusters == gi["n_clusters"]
+
+
+@pytest.mark.parametrize("gamma", [1.0, 10.0, 100.0])
+def test_plain_config_mixed_converged(cc, gamma):
+    X, M, E, w = plain_problem()
+    X = as_f32_values(X)
+    st, info = oracle_jacobi(X, M, E, w).solve(gamma, mm.Opts(proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        gi = g.solve(gamma)
+        U = g.U(torch.float64).cpu().numpy()
+        lab, ncl = g.labels()
+        fused = g.fused_edges().cpu().numpy().astype(bool)
+    assert gi["converged"] == 1
+    assert rel_max(U, st.U) <= 1e-5
+    assert np.array_equal(lab.cpu().numpy(), info.labels)
+    assert ncl == info.n_clusters
+    assert np.array_equal(fused, info.fused)
+
+
+def test_reduced_expression_path_mixed(cc):
+    """Expression-like recipe at n=100, p=150 (two feature tiles, the second
+    ragged) with 5% missing entries: a
+    warm-started path; every gamma matches within 1e-5 with equal labels."""
+    X, M, E, w, gam = reduced_expression(n=100, p=150)
+    gam = [0.3, 3.0, 30.0, 100.0]
+    # missing entries at small gamma converge slowly (the loss is flat in
+    # them); both sides stop at the same cap when the test has not passed
+    cap = 4000
+    _, infos, Us = oracle_jacobi(X, M, E, w).solve_path(gam, mm.Opts(proj="jacobi:1", max_iter=cap))
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        ginfos, lab, Up = g.solve_path(gam, labels=True, U_path=True, max_iter=cap)
+    lab = lab.cpu().numpy()
+    Up = Up.cpu().numpy()
+    for k in range(len(gam)):
+        assert ginfos[k]["converged"] == int(infos[k].converged)
+        assert abs(ginfos[k]["iters"] - infos[k].iters) <= mm.DEFAULT_TEST_EVERY
+        assert rel_max(Up[k], Us[k]) <= 1e-5, (gam[k], rel_max(Up[k], Us[k]))
+        assert np.array_equal(lab[k], infos[k].labels), gam[k]
+    assert len(set(i.n_clusters for i in infos)) > 1  # the path spans fusion
+
+
+def test_f32_precision_plain(cc):
+    X, M, E, w = plain_problem()
+    X = as_f32_values(X)
+    st, info = oracle_jacobi(X, M, E, w).solve(10.0, mm.Opts(proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, "f32") as g:
+        g.solve(10.0, max_iter=60000)
+        U = g.U(torch.float64).cpu().numpy()
+        lab, _ = g.labels()
+    assert rel_max(U, st.U) <= 2e-4
+    assert np.array_equal(lab.cpu().numpy(), info.labels)
+
+
+# ------------------------------------------------------------ edge cases
+def test_gamma_zero_and_isolated_points(cc):
+    X, M, E, w, _ = reduced_expression(n=80, p=20)
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        g.solve(0.0, tol=0.0, max_iter=30)
+        U = g.U(torch.float64).cpu().numpy()
+    obs = M
+    assert np.array_equal(U[obs], X[obs])
+    # no edges at all: U = X for any gamma
+    with _gpu(cc, X, M, np.zeros((0, 2), int), np.zeros(0), "mixed") as g:
+        info = g.solve(5.0, tol=0.0, max_iter=10)
+        U = g.U(torch.float64).cpu().numpy()
+        lab, ncl = g.labels()
+    assert np.array_equal(U[obs], X[obs])
+    assert ncl == X.shape[0] and info["n_clusters"] == X.shape[0]
+
+
+@pytest.mark.parametrize("n,p", [(1, 1), (1, 5), (2, 1), (3, 300), (9, 1)])
+def test_tiny_shapes(cc, n, p):
+    rng = np.random.default_rng(n * 100 + p)
+    X = as_f32_values(rng.normal(size=(n, p)))
+    E = np.array([(i, j) for i in range(n) for j in range(i + 1, n)], dtype=np.int64).reshape(-1, 2)
+    w = np.ones(len(E))
+    st, info = oracle_jacobi(X, None, E, w).solve(0.7, mm.Opts(proj="jacobi:1", tol=0, max_iter=40))
+    with _gpu(cc, X, None, E, w, "f64") as g:
+        g.solve(0.7, tol=0.0, max_iter=40)
+        U = g.U(torch.float64).cpu().numpy()
+        lab, ncl = g.labels()
+    assert rel_max(U, st.U) < 1e-11
+    assert np.array_equal(lab.cpu().numpy(), info.labels)
+
+
+def test_all_observed_mask_equals_no_mask(cc):
+    X, _, E, w = plain_problem()
+    X = as_f32_values(X)
+    with _gpu(cc, X, None, E, w, "mixed") as g:
+        g.solve(10.0, tol=0.0, max_iter=100)
+        a = g.U(torch.float64).cpu().numpy()
+    with _gpu(cc, X, np.ones(X.shape, bool), E, w, "mixed") as g:
+        g.solve(10.0, tol=0.0, max_iter=100)
+        b = g.U(torch.float64).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_deterministic_repeat(cc):
+    X, M, E, w, _ = reduced_expression()
+    outs = []
+    for _ in range(2):
+        with _gpu(cc, X, M, E, w, "mixed") as g:
+            g.solve(5.0, tol=0.0, max_iter=300)
+            outs.append(g.U(torch.float64).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_state_export_import_resumes_path_bitwise(cc):
+    X, M, E, w, _ = reduced_expression()
+    gam = [0.5, 2.0, 8.0, 30.0]
+    kw = dict(tol=1e-6, max_iter=5000)
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        _, lab_all, U_all = g.solve_path(gam, U_path=True, **kw)
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        g.solve_path(gam[:2], **kw)
+        blob = g.export_state()
+    with _gpu(cc, X, M, E, w, "mixed") as g2:
+        g2.import_state(blob)
+        _, lab2, U2 = g2.solve_path(gam[2:], U_path=True, **kw)
+    assert torch.equal(U2, U_all[2:])
+    assert torch.equal(lab2, lab_all[2:])
+
+
+def test_invalid_inputs_rejected(cc):
+    X, M, E, w = plain_problem()
+    Xb = X.copy()
+    Xb[3, 2] = np.nan
+    with pytest.raises(cc.CCError) as ei:
+        _gpu(cc, Xb, None, E, w, "mixed")
+    assert ei.value.status == 1
+    with pytest.raises(cc.CCError):
+        _gpu(cc, X, None, E[:, ::-1].copy(), w, "mixed")   # i > j
+    with pytest.raises(cc.CCError):
+        _gpu(cc, X, None, np.vstack([E, E[:1]]), np.r_[w, w[:1]], "mixed")  # duplicate
+    with pytest.raises(cc.CCError):
+        _gpu(cc, X, None, E, -w, "mixed")

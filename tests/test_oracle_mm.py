@@ -193,6 +193,28 @@ def test_stopping_rule_semantics():
     assert info.iters == 37 and not info.converged
     _, info2 = prob.solve(1.0, mm.Opts(tol=1e-3))
     assert info2.converged and info2.iters >= mm.MIN_TEST_ITER + 1
+    assert info2.iters % mm.DEFAULT_TEST_EVERY == 0
+    _, info3 = prob.solve(1.0, mm.Opts(tol=1e-3, test_every=1))
+    assert info3.converged and info3.iters >= mm.MIN_TEST_ITER + 1
+
+
+def test_window_test_equals_one_step_test_for_k1():
+    """K = 1 is the plain test sqrt(||U_{m+1}-U_m||^2 + ||A_m-A_{m-1}||^2)."""
+    X, M, E, w = mixture_problem(16)
+    prob = mm.Problem(X, M, E, w)
+    rho, eps = prob.constants(1.0, mm.Opts())
+    eta = np.sqrt(eps) / rho
+    st = prob.initial_state()
+    expect = None
+    for m in range(5000):
+        st2, dg = prob.iterate(1.0, rho, eps, st, "exact")
+        r = np.sqrt(dg["dU2"] + dg["dA2"])
+        if m >= mm.MIN_TEST_ITER and r <= 1e-4 * eta * max(1.0, np.linalg.norm(st2.U)):
+            expect = m + 1
+            break
+        st = st2
+    _, info = prob.solve(1.0, mm.Opts(tol=1e-4, test_every=1))
+    assert info.converged and info.iters == expect
 
 
 def test_jacobi_fixed_point_equals_exact():
