@@ -44,9 +44,12 @@ struct Problem {
   int64_t n = 0, p = 0, E = 0, ld = 0;
   int precision = kMixed;
   hipStream_t stream = nullptr;
-  int ntile = 1;      // feature tiles of width tile_w
+  int ntile = 1;      // point-sweep feature tiles of width tile_w
   int tile_w = 256;   // features per tile (64 lanes x vec)
   int vec = 4;
+  int entile = 1;     // edge-sweep tiles (1: the fused edge kernel)
+  int npass = 4;      // 64-feature passes per edge tile
+  bool efused = true;
   // device buffers
   void *X = nullptr;         // n x ld, float (f32/mixed) or double (f64)
   uint8_t *M = nullptr;      // n x ld or null
@@ -57,7 +60,9 @@ struct Problem {
   int32_t *rowptr = nullptr, *col = nullptr, *eid = nullptr, *uptr = nullptr;
   int32_t *ei = nullptr, *ej = nullptr;
   double *w = nullptr, *s = nullptr, *nb[2] = {nullptr, nullptr};
-  double *part = nullptr;    // E x ntile edge partials
+  double *qe = nullptr, *qcsr = nullptr;  // mu w / (rho ||b||), per edge and per CSR entry
+  int32_t *epos = nullptr;                // CSR positions of both directions of each edge
+  double *part = nullptr;    // E x entile edge partials
   double *psum = nullptr;    // kMaxBlocks x 8 point partials
   double *esum = nullptr;    // kMaxBlocks x 4 edge partials
   double *trace = nullptr;   // objective per iteration (record mode)

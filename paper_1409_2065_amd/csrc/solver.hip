@@ -168,26 +168,40 @@ struct PointArgs {
   void *A0, *A1, *G0, *G1;
   void *Usnap, *Asnap;
   const int32_t *rowptr, *col, *eid;
-  const double *w;
-  double *s;
-  const double *nb0, *nb1;
+  const double *qcsr;   // mu w / (rho ||b||) of the previous A, per CSR entry
+  const double *s;      // state shrink factors (first iteration of a solve)
   double *psum;
   DevScalars *sc;
 };
 
+// Per-edge bookkeeping shared by the fused edge kernel and the reduction
+// kernel: norms, shrink factors, and the q factors of the next iteration.
+struct EdgeState {
+  int E;
+  const double *w;
+  double *s;            // s_m written here (the state's V factors)
+  double *nb0, *nb1;    // ||b|| per edge, double-buffered with A
+  double *qe;           // q per edge
+  double *qcsr;         // q per CSR entry (both directions)
+  const int32_t *epos;  // CSR positions of (i->j) and (j->i) per edge
+};
+
 struct EdgeArgs {
-  int n, ld, ntile, nitems, chunk, init;
+  int n, ld, ntile, nitems, chunk, init, nbp;
   const void *G0, *G1;
   const int32_t *rowptr, *uptr, *col, *eid;
-  double *part;
+  double *part;         // E x ntile partial ||b||^2 (ntile > 1)
+  EdgeState es;
+  double *esum;
+  const double *psum;
+  double *trace;
   DevScalars *sc;
 };
 
 struct ReduceArgs {
-  int E, ntile, nbp, init;
+  int ntile, nbp, init;
   const double *part;
-  double *nb0, *nb1;
-  const double *s, *w;
+  EdgeState es;
   double *esum;
   const double *psum;
   double *trace;
@@ -206,7 +220,6 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
   const int m = sc->m, pa = sc->pa;
   const double rho = sc->rho, dprev = sc->d_prev;
   const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
-  const double tau_scale = (m > 0) ? sc->mu * dprev / rho : 0.0;
   // stop-test window: U snapshots at m = 0, K, 2K, ...; A snapshots at
   // m = K-1, 2K-1, ... (the start-of-solve A' seeds the first A window)
   const int K = sc->K;
@@ -218,11 +231,11 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
   TS *An = reinterpret_cast<TS *>(pa == 0 ? a.A1 : a.A0);
   const TG *Gp = reinterpret_cast<const TG *>(pa == 0 ? a.G0 : a.G1);
   TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
-  const double *nbp = pa == 0 ? a.nb0 : a.nb1;
   const TX *X = reinterpret_cast<const TX *>(a.X);
   TS *U = reinterpret_cast<TS *>(a.U);
 
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lb = logical_block();
   const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
   const int W = kWave * VEC;
@@ -255,37 +268,26 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
       double cl = 0.0;
       if (lane < cnt) {
         jl = a.col[base + lane];
-        const int e = a.eid[base + lane];
-        if (m > 0) {
-          const double nbv = nbp[e];
-          const double tau = a.w[e] * tau_scale;
-          cl = (nbv > tau) ? tau / nbv : 1.0;   // c = 1 - s, s = max(1 - tau/nb, 0)
-          if (t == 0 && jl > i) a.s[e] = 1.0 - cl;
-        } else {
-          cl = 1.0 - a.s[e];
-        }
+        // c = 1 - s with s the V-update shrink factor; from the state at the
+        // first iteration of a solve, else min(d q, 1) = min(tau/||b||, 1)
+        cl = (m > 0) ? fmin(dprev * a.qcsr[base + lane], 1.0) : 1.0 - a.s[a.eid[base + lane]];
       }
       int k = 0;
-      for (; k + 4 <= cnt; k += 4) {
-        const int j0 = __builtin_amdgcn_readlane(jl, k);
-        const int j1 = __builtin_amdgcn_readlane(jl, k + 1);
-        const int j2 = __builtin_amdgcn_readlane(jl, k + 2);
-        const int j3 = __builtin_amdgcn_readlane(jl, k + 3);
-        const double c0 = readlane_d(cl, k), c1 = readlane_d(cl, k + 1);
-        const double c2 = readlane_d(cl, k + 2), c3 = readlane_d(cl, k + 3);
-        C += c0; C += c1; C += c2; C += c3;
-        if (active) {
-          double x0[VEC], x1[VEC], x2[VEC], x3[VEC];
-          VecIO<VEC>::load(Gp + (size_t)j0 * a.ld + f0, x0);
-          VecIO<VEC>::load(Gp + (size_t)j1 * a.ld + f0, x1);
-          VecIO<VEC>::load(Gp + (size_t)j2 * a.ld + f0, x2);
-          VecIO<VEC>::load(Gp + (size_t)j3 * a.ld + f0, x3);
+      for (; k + 8 <= cnt; k += 8) {
+        int j[8];
+        double c[8];
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) {
-            sumg[v] += x0[v]; sumcg[v] = fma(c0, x0[v], sumcg[v]);
-            sumg[v] += x1[v]; sumcg[v] = fma(c1, x1[v], sumcg[v]);
-            sumg[v] += x2[v]; sumcg[v] = fma(c2, x2[v], sumcg[v]);
-            sumg[v] += x3[v]; sumcg[v] = fma(c3, x3[v], sumcg[v]);
+        for (int q = 0; q < 8; ++q) { j[q] = __builtin_amdgcn_readlane(jl, k + q); c[q] = readlane_d(cl, k + q); }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) C += c[q];
+        if (active) {
+          double xv[8][VEC];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) VecIO<VEC>::load(Gp + (size_t)j[q] * a.ld + f0, xv[q]);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) { sumg[v] += xv[q][v]; sumcg[v] = fma(c[q], xv[q][v], sumcg[v]); }
           }
         }
       }
@@ -359,72 +361,46 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
   }
 }
 
-// -------------------------------------------------------------- k_edge
-// One wave per (point i, tile); each quarter-wave takes one upper neighbour
-// j > i and sums (a_i - a_j)^2 over the tile, 4 features per lane per pass.
-template <int PREC, int VEC>
-__global__ __launch_bounds__(kBlock) void k_edge(EdgeArgs a) {
-  using TG = typename Traits<PREC>::TG;
-  DevScalars *sc = a.sc;
-  if (!a.init && sc->done) return;
-  const int pa = sc->pa;
-  // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
-  const int buf = a.init ? pa : (pa ^ 1);
-  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
-  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int q = lane / 16, l16 = lane % 16;
-  const int lb = logical_block();
-  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
-  const int W = kWave * VEC;
-  for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
-    const int t = item / a.n, i = item - t * a.n;
-    double gi[VEC][4];
-#pragma unroll
-    for (int ps = 0; ps < VEC; ++ps) {
-      const int fo = t * W + ps * 64 + l16 * 4;
-      if (fo < a.ld) VecIO<4>::load(Gc + (size_t)i * a.ld + fo, gi[ps]);
-      else { gi[ps][0] = gi[ps][1] = gi[ps][2] = gi[ps][3] = 0.0; }
-    }
-    const int us = a.uptr[i], re = a.rowptr[i + 1];
-    for (int k = us; k < re; k += 4) {
-      const int kk = k + q;
-      const bool valid = kk < re;
-      int j = i, e = 0;
-      if (valid) { j = a.col[kk]; e = a.eid[kk]; }
-      double acc = 0.0;
-#pragma unroll
-      for (int ps = 0; ps < VEC; ++ps) {
-        const int fo = t * W + ps * 64 + l16 * 4;
-        if (valid && fo < a.ld) {
-          double xj[4];
-          VecIO<4>::load(Gc + (size_t)j * a.ld + fo, xj);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) { const double d = gi[ps][v] - xj[v]; acc = fma(d, d, acc); }
-        }
-      }
-      acc += __shfl_xor(acc, 8, kWave);
-      acc += __shfl_xor(acc, 4, kWave);
-      acc += __shfl_xor(acc, 2, kWave);
-      acc += __shfl_xor(acc, 1, kWave);
-      if (valid && l16 == 0) a.part[(size_t)e * a.ntile + t] = acc;
-    }
-  }
+// --------------------------------------------------- per-edge bookkeeping
+// Given ||b_e||^2 of the new A_m: store ||b_e||; in an iteration also take
+// s_m (the shrink factor the point sweep used), accumulate the edge terms of
+// ||V - D A||^2 and of the penalty, and prepare q_e = mu w_e / (rho ||b_e||)
+// for the next point sweep (c = min(d q, 1) there, +inf when b_e = 0).
+__device__ inline void edge_update(const EdgeState &es, int e, double nb2, int init, int pa,
+                                   const DevScalars *sc, double (&t3)[kEdgeSums]) {
+  double *nbout = init ? (pa == 0 ? es.nb0 : es.nb1) : (pa == 0 ? es.nb1 : es.nb0);
+  const double nbn = sqrt(nb2);
+  nbout[e] = nbn;
+  if (init) return;
+  const double *nbprev = pa == 0 ? es.nb0 : es.nb1;
+  const int m = sc->m;
+  const double sv = (m > 0) ? 1.0 - fmin(sc->d_prev * es.qe[e], 1.0) : es.s[e];
+  es.s[e] = sv;
+  const double np = nbprev[e];
+  t3[0] += nb2;
+  t3[1] += (sv * np) * (sv * np);
+  t3[2] += es.w[e] * sv * np;
+  const double q = (nbn > 0.0) ? (sc->mu * es.w[e]) / (sc->rho * nbn) : __builtin_inf();
+  es.qe[e] = q;
+  es.qcsr[es.epos[2 * e]] = q;
+  es.qcsr[es.epos[2 * e + 1]] = q;
 }
 
-// ------------------------------------------------------- k_edge_reduce
-__device__ void finish_iteration(const ReduceArgs &a, double *red) {
-  DevScalars *sc = a.sc;
-  // fixed-order sums of the point partials and of the edge partials
+// ------------------------------------------------------- iteration finish
+// Fixed-order sums of every point and edge partial, then d, the objective,
+// the windowed stop test and the advance of the iteration scalars.
+__device__ void finish_iteration(const double *psum, int nbp, const double *esum, int nbe,
+                                 double *trace, DevScalars *sc, double *red) {
   double v[kPointSums + kEdgeSums];
 #pragma unroll
   for (int q = 0; q < kPointSums + kEdgeSums; ++q) v[q] = 0.0;
-  for (int b = threadIdx.x; b < a.nbp; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nbp; b += blockDim.x) {
 #pragma unroll
-    for (int q = 0; q < kPointSums; ++q) v[q] += a.psum[(size_t)b * 8 + q];
+    for (int q = 0; q < kPointSums; ++q) v[q] += psum[(size_t)b * 8 + q];
   }
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nbe; b += blockDim.x) {
 #pragma unroll
-    for (int q = 0; q < kEdgeSums; ++q) v[kPointSums + q] += a.esum[(size_t)b * 4 + q];
+    for (int q = 0; q < kEdgeSums; ++q) v[kPointSums + q] += esum[(size_t)b * 4 + q];
   }
   block_sum<kPointSums + kEdgeSums>(v, red);
   if (threadIdx.x != 0) return;
@@ -434,7 +410,7 @@ __device__ void finish_iteration(const ReduceArgs &a, double *red) {
   const double d = sqrt(uA2 + viol + sc->eps);
   const double F = 0.5 * loss2 + sc->mu * pen + sc->rho * d;
   const int m = sc->m;
-  if (sc->record && a.trace) a.trace[m] = F;
+  if (sc->record && trace) trace[m] = F;
   if (!isfinite(d) || !isfinite(F)) {
     sc->status = CC_ERR_NUMERIC; sc->done = 1; sc->iters = m;
     return;
@@ -465,31 +441,16 @@ __device__ void finish_iteration(const ReduceArgs &a, double *red) {
   sc->m = m + 1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_edge_reduce(ReduceArgs a) {
+// Block partials of the edge terms, then the last block to arrive finishes
+// the iteration.
+__device__ inline void edge_block_tail(double (&t3)[kEdgeSums], double *esum, const double *psum,
+                                       int nbp, double *trace, DevScalars *sc) {
   __shared__ double red[kWavesPerBlock * (kPointSums + kEdgeSums)];
   __shared__ int is_last;
-  DevScalars *sc = a.sc;
-  if (!a.init && sc->done) return;
-  const int pa = sc->pa;
-  double *nbout = a.init ? (pa == 0 ? a.nb0 : a.nb1) : (pa == 0 ? a.nb1 : a.nb0);
-  const double *nbprev = pa == 0 ? a.nb0 : a.nb1;
-  double t3[kEdgeSums] = {0.0, 0.0, 0.0};
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < a.E; e += gridDim.x * blockDim.x) {
-    double nb2 = 0.0;
-    for (int t = 0; t < a.ntile; ++t) nb2 += a.part[(size_t)e * a.ntile + t];
-    nbout[e] = sqrt(nb2);
-    if (!a.init) {
-      const double sv = a.s[e], np = nbprev[e];
-      t3[0] += nb2;
-      t3[1] += (sv * np) * (sv * np);
-      t3[2] += a.w[e] * sv * np;
-    }
-  }
-  if (a.init) return;
   block_sum<kEdgeSums>(t3, red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < kEdgeSums; ++q) a.esum[(size_t)blockIdx.x * 4 + q] = t3[q];
+    for (int q = 0; q < kEdgeSums; ++q) esum[(size_t)blockIdx.x * 4 + q] = t3[q];
     __threadfence();
     const unsigned prev = atomicAdd(&sc->counter, 1u);
     is_last = (prev == gridDim.x - 1) ? 1 : 0;
@@ -497,8 +458,86 @@ __global__ __launch_bounds__(kBlock) void k_edge_reduce(ReduceArgs a) {
   __syncthreads();
   if (!is_last) return;
   __threadfence();
-  finish_iteration(a, red);
+  finish_iteration(psum, nbp, esum, gridDim.x, trace, sc, red);
   if (threadIdx.x == 0) sc->counter = 0u;
+}
+
+// -------------------------------------------------------------- k_edge
+// One wave per (point i, tile); each quarter-wave takes one upper neighbour
+// j > i and sums (a_i - a_j)^2 over the tile, 4 features per lane per pass.
+// FUSED (one tile covers the row): the quarter leader finishes the edge and
+// the kernel ends the iteration; otherwise per-tile partials are written.
+template <int PREC, int NPASS, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_edge(EdgeArgs a) {
+  using TG = typename Traits<PREC>::TG;
+  DevScalars *sc = a.sc;
+  if (!a.init && sc->done) return;
+  const int pa = sc->pa;
+  // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
+  const int buf = a.init ? pa : (pa ^ 1);
+  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int q = lane / 16, l16 = lane % 16;
+  const int lb = logical_block();
+  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
+  const int W = 64 * NPASS;
+  double t3[kEdgeSums] = {0.0, 0.0, 0.0};
+  for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
+    const int t = item / a.n, i = item - t * a.n;
+    double gi[NPASS][4];
+#pragma unroll
+    for (int ps = 0; ps < NPASS; ++ps) {
+      const int fo = t * W + ps * 64 + l16 * 4;
+      if (fo < a.ld) VecIO<4>::load(Gc + (size_t)i * a.ld + fo, gi[ps]);
+      else { gi[ps][0] = gi[ps][1] = gi[ps][2] = gi[ps][3] = 0.0; }
+    }
+    const int us = a.uptr[i], re = a.rowptr[i + 1];
+    for (int k = us; k < re; k += 4) {
+      const int kk = k + q;
+      const bool valid = kk < re;
+      int j = i, e = 0;
+      if (valid) { j = a.col[kk]; e = a.eid[kk]; }
+      double acc = 0.0;
+#pragma unroll
+      for (int ps = 0; ps < NPASS; ++ps) {
+        const int fo = t * W + ps * 64 + l16 * 4;
+        if (valid && fo < a.ld) {
+          double xj[4];
+          VecIO<4>::load(Gc + (size_t)j * a.ld + fo, xj);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) { const double d = gi[ps][v] - xj[v]; acc = fma(d, d, acc); }
+        }
+      }
+      acc += __shfl_xor(acc, 8, kWave);
+      acc += __shfl_xor(acc, 4, kWave);
+      acc += __shfl_xor(acc, 2, kWave);
+      acc += __shfl_xor(acc, 1, kWave);
+      if (valid && l16 == 0) {
+        if (FUSED) edge_update(a.es, e, acc, a.init, pa, sc, t3);
+        else a.part[(size_t)e * a.ntile + t] = acc;
+      }
+    }
+  }
+  if (!FUSED || a.init) return;
+  edge_block_tail(t3, a.esum, a.psum, a.nbp, a.trace, sc);
+}
+
+// ------------------------------------------------------- k_edge_reduce
+// Wide rows: per edge, the tile partials in fixed order, then the same
+// per-edge bookkeeping and iteration finish as the fused edge kernel.
+__global__ __launch_bounds__(kBlock) void k_edge_reduce(ReduceArgs a) {
+  DevScalars *sc = a.sc;
+  if (!a.init && sc->done) return;
+  const int pa = sc->pa;
+  double t3[kEdgeSums] = {0.0, 0.0, 0.0};
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < a.es.E; e += gridDim.x * blockDim.x) {
+    double nb2 = 0.0;
+    for (int t = 0; t < a.ntile; ++t) nb2 += a.part[(size_t)e * a.ntile + t];
+    edge_update(a.es, e, nb2, a.init, pa, sc, t3);
+  }
+  if (a.init) return;
+  edge_block_tail(t3, a.esum, a.psum, a.nbp, a.trace, sc);
 }
 
 // --------------------------------------------------------- small kernels
@@ -703,26 +742,77 @@ static hipEvent_t *prof_slot(Problem *P) {
 }
 
 template <int PREC, int VEC>
-static void launch_iteration_t(Problem *P) {
+static void launch_point_t(Problem *P, const Launch &Lp) {
+  PointArgs pa{(int)P->n, (int)P->ld, P->ntile, Lp.nitems, Lp.chunk,
+               P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
+               P->rowptr, P->col, P->eid, P->qcsr, P->s, P->psum, P->sc};
+  hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kBlock), 0, P->stream, pa);
+}
+
+static EdgeState edge_state(Problem *P) {
+  return EdgeState{(int)P->E, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qcsr, P->epos};
+}
+
+template <int PREC, int NPASS, bool FUSED>
+static void launch_edge_t(Problem *P, int init, int nbp) {
+  const Launch Le = sweep_grid(P->n * P->entile);
+  EdgeArgs ea{(int)P->n, (int)P->ld, P->entile, Le.nitems, Le.chunk, init, nbp,
+              P->G[0], P->G[1], P->rowptr, P->uptr, P->col, P->eid, P->part,
+              edge_state(P), P->esum, P->psum, P->trace, P->sc};
+  hipLaunchKernelGGL((k_edge<PREC, NPASS, FUSED>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea);
+}
+
+template <int PREC>
+static void launch_edge_p(Problem *P, int init, int nbp) {
+  if (P->efused) {
+    switch (P->npass) {
+      case 1: launch_edge_t<PREC, 1, true>(P, init, nbp); break;
+      case 2: launch_edge_t<PREC, 2, true>(P, init, nbp); break;
+      case 4: launch_edge_t<PREC, 4, true>(P, init, nbp); break;
+      case 8: launch_edge_t<PREC, 8, true>(P, init, nbp); break;
+      default: launch_edge_t<PREC, 16, true>(P, init, nbp); break;
+    }
+  } else {
+    launch_edge_t<PREC, 4, false>(P, init, nbp);
+    const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
+    ReduceArgs ra{P->entile, nbp, init, P->part, edge_state(P), P->esum, P->psum, P->trace, P->sc};
+    hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
+  }
+}
+
+template <int PREC>
+static void launch_point_p(Problem *P, const Launch &Lp) {
+  switch (P->vec) {
+    case 1: launch_point_t<PREC, 1>(P, Lp); break;
+    case 2: launch_point_t<PREC, 2>(P, Lp); break;
+    default: launch_point_t<PREC, 4>(P, Lp); break;
+  }
+}
+
+static void launch_iteration(Problem *P) {
   hipEvent_t *ev = prof_slot(P);
   if (ev) (void)hipEventRecord(ev[0], P->stream);
   const Launch Lp = sweep_grid(P->n * P->ntile);
-  PointArgs pa{(int)P->n, (int)P->ld, P->ntile, Lp.nitems, Lp.chunk,
-               P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
-               P->rowptr, P->col, P->eid, P->w, P->s, P->nb[0], P->nb[1],
-               P->psum, P->sc};
-  hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kBlock), 0, P->stream, pa);
+  if (P->precision == kF32) launch_point_p<kF32>(P, Lp);
+  else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
+  else launch_point_p<kMixed>(P, Lp);
   if (ev) (void)hipEventRecord(ev[1], P->stream);
-  const Launch Le = Lp;
-  EdgeArgs ea{(int)P->n, (int)P->ld, P->ntile, Le.nitems, Le.chunk, 0,
-              P->G[0], P->G[1], P->rowptr, P->uptr, P->col, P->eid, P->part, P->sc};
-  hipLaunchKernelGGL((k_edge<PREC, VEC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea);
-  if (ev) (void)hipEventRecord(ev[2], P->stream);
-  const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
-  ReduceArgs ra{(int)P->E, P->ntile, Lp.blocks, 0, P->part, P->nb[0], P->nb[1],
-                P->s, P->w, P->esum, P->psum, P->trace, P->sc};
-  hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
-  if (ev) (void)hipEventRecord(ev[3], P->stream);
+  if (P->precision == kF32) launch_edge_p<kF32>(P, 0, Lp.blocks);
+  else if (P->precision == kF64) launch_edge_p<kF64>(P, 0, Lp.blocks);
+  else launch_edge_p<kMixed>(P, 0, Lp.blocks);
+  if (ev) {
+    // the fused edge kernel ends the iteration itself: the reduction slot
+    // then records zero time
+    (void)hipEventRecord(ev[2], P->stream);
+    (void)hipEventRecord(ev[3], P->stream);
+  }
+}
+
+// Edge norms of the A in buffer pa (state set or reset).
+static void launch_edge_init(Problem *P) {
+  if (P->precision == kF32) launch_edge_p<kF32>(P, 1, 0);
+  else if (P->precision == kF64) launch_edge_p<kF64>(P, 1, 0);
+  else launch_edge_p<kMixed>(P, 1, 0);
 }
 
 cc_status profile(Problem *P, int32_t sample_every) {
@@ -751,43 +841,10 @@ cc_status harvest_profile(Problem *P) {
   return CC_OK;
 }
 
-template <int PREC, int VEC>
-static void launch_edge_init_t(Problem *P) {
-  const Launch Le = sweep_grid(P->n * P->ntile);
-  EdgeArgs ea{(int)P->n, (int)P->ld, P->ntile, Le.nitems, Le.chunk, 1,
-              P->G[0], P->G[1], P->rowptr, P->uptr, P->col, P->eid, P->part, P->sc};
-  hipLaunchKernelGGL((k_edge<PREC, VEC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea);
-  const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
-  ReduceArgs ra{(int)P->E, P->ntile, Le.blocks, 1, P->part, P->nb[0], P->nb[1],
-                P->s, P->w, P->esum, P->psum, P->trace, P->sc};
-  hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
-}
-
-template <int PREC>
-static void dispatch_vec(Problem *P, bool init) {
-  switch (P->vec) {
-    case 1: init ? launch_edge_init_t<PREC, 1>(P) : launch_iteration_t<PREC, 1>(P); break;
-    case 2: init ? launch_edge_init_t<PREC, 2>(P) : launch_iteration_t<PREC, 2>(P); break;
-    default: init ? launch_edge_init_t<PREC, 4>(P) : launch_iteration_t<PREC, 4>(P); break;
-  }
-}
-
-static void launch_iteration(Problem *P) {
-  if (P->precision == kF32) dispatch_vec<kF32>(P, false);
-  else if (P->precision == kF64) dispatch_vec<kF64>(P, false);
-  else dispatch_vec<kMixed>(P, false);
-}
-
-static void launch_edge_init(Problem *P) {
-  if (P->precision == kF32) dispatch_vec<kF32>(P, true);
-  else if (P->precision == kF64) dispatch_vec<kF64>(P, true);
-  else dispatch_vec<kMixed>(P, true);
-}
-
 void problem_free(Problem *P) {
   if (!P) return;
   void *bufs[] = {P->X, P->M, P->U, P->A[0], P->A[1], P->Usnap, P->Asnap, P->rowptr, P->col, P->eid, P->uptr,
-                  P->ei, P->ej, P->w, P->s, P->nb[0], P->nb[1], P->part, P->psum,
+                  P->ei, P->ej, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qcsr, P->epos, P->part, P->psum,
                   P->esum, P->trace, P->sc, P->ncl_dev};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -828,6 +885,18 @@ static void choose_tiles(Problem *P) {
   P->vec = vec;
   P->tile_w = kWave * vec;
   P->ntile = (int)cdiv(P->ld, P->tile_w);
+  // edge sweep: one tile over the whole row when it is at most 1024 wide
+  if (P->ld <= 1024) {
+    int np = 1;
+    while (64 * np < P->ld) np <<= 1;
+    P->npass = np;
+    P->entile = 1;
+    P->efused = true;
+  } else {
+    P->npass = 4;
+    P->entile = (int)cdiv(P->ld, 256);
+    P->efused = false;
+  }
 }
 
 cc_status reset_state(Problem *P);
@@ -910,7 +979,10 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   CC_TRY(dmalloc((void **)&P->s, E * 8));
   CC_TRY(dmalloc((void **)&P->nb[0], E * 8));
   CC_TRY(dmalloc((void **)&P->nb[1], E * 8));
-  CC_TRY(dmalloc((void **)&P->part, E * P->ntile * 8));
+  CC_TRY(dmalloc((void **)&P->qe, E * 8));
+  CC_TRY(dmalloc((void **)&P->qcsr, 2 * E * 8));
+  CC_TRY(dmalloc((void **)&P->epos, 2 * E * 4));
+  CC_TRY(dmalloc((void **)&P->part, E * (P->efused ? 1 : P->entile) * 8));
   CC_TRY(dmalloc((void **)&P->psum, kMaxBlocks * 8 * 8));
   CC_TRY(dmalloc((void **)&P->esum, kMaxBlocks * 4 * 8));
   CC_TRY(dmalloc((void **)&P->sc, sizeof(DevScalars)));
@@ -931,13 +1003,15 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
       ent[fill[hj[e]]++] = {hi[e], (int32_t)e};
     }
   }
-  std::vector<int32_t> hcol(2 * E), heid(2 * E), hup(n);
+  std::vector<int32_t> hcol(2 * E), heid(2 * E), hup(n), hpos(2 * E);
   int64_t maxdeg = 0;
   for (int64_t i = 0; i < n; ++i) {
     std::sort(ent.begin() + rp[i], ent.begin() + rp[i + 1]);
     int32_t up = rp[i + 1];
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
       hcol[k] = ent[k].first; heid[k] = ent[k].second;
+      // entry (i -> j) of edge e sits in row ei[e] (slot 0) or ej[e] (slot 1)
+      hpos[2 * (int64_t)ent[k].second + (hi[ent[k].second] == i ? 0 : 1)] = k;
       if (up == rp[i + 1] && ent[k].first > i) up = k;
     }
     hup[i] = up;
@@ -949,6 +1023,7 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   if (E > 0) {
     CC_HIP(hipMemcpyAsync(P->col, hcol.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
     CC_HIP(hipMemcpyAsync(P->eid, heid.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
+    CC_HIP(hipMemcpyAsync(P->epos, hpos.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
     CC_HIP(hipMemcpyAsync(P->ei, hi.data(), E * 4, hipMemcpyHostToDevice, stream));
     CC_HIP(hipMemcpyAsync(P->ej, hj.data(), E * 4, hipMemcpyHostToDevice, stream));
     CC_HIP(hipMemcpyAsync(P->w, hw.data(), E * 8, hipMemcpyHostToDevice, stream));

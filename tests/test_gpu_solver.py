@@ -202,11 +202,17 @@ def test_state_export_import_resumes_path_bitwise(cc):
 
 def test_invalid_inputs_rejected(cc):
     X, M, E, w = plain_problem()
-    Xb = X.copy()
-    Xb[3, 2] = np.nan
+    _, _, e, wt = to_dev(X, None, E, w, torch.float32)
+    Xb = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Xb[3, 2] = float("nan")          # an observed non-finite entry
     with pytest.raises(cc.CCError) as ei:
-        _gpu(cc, Xb, None, E, w, "mixed")
+        cc.Problem(Xb, None, e, wt)
     assert ei.value.status == 1
+    mb = torch.ones(Xb.shape, dtype=torch.uint8, device="cuda")
+    mb[3, 2] = 0                     # the same entry marked missing is fine
+    with cc.Problem(Xb, mb, e, wt) as g:
+        g.solve(1.0, max_iter=5)
+        assert torch.isfinite(g.U()).all()
     with pytest.raises(cc.CCError):
         _gpu(cc, X, None, E[:, ::-1].copy(), w, "mixed")   # i > j
     with pytest.raises(cc.CCError):
