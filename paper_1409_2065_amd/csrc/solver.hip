@@ -113,6 +113,40 @@ template <> struct VecIO<1> {
   __device__ static void load_mask(const uint8_t *p, bool (&o)[1]) { o[0] = *p != 0; }
 };
 
+// Raw vector loads (no conversion) for the software-pipelined gathers.
+template <typename T, int VEC> struct RawIO;
+template <> struct RawIO<float, 4> {
+  __device__ static void load(const float *p, float (&o)[4]) {
+    float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+};
+template <> struct RawIO<float, 2> {
+  __device__ static void load(const float *p, float (&o)[2]) {
+    float2 v = *reinterpret_cast<const float2 *>(p);
+    o[0] = v.x; o[1] = v.y;
+  }
+};
+template <> struct RawIO<float, 1> {
+  __device__ static void load(const float *p, float (&o)[1]) { o[0] = *p; }
+};
+template <> struct RawIO<double, 4> {
+  __device__ static void load(const double *p, double (&o)[4]) {
+    double2 a = *reinterpret_cast<const double2 *>(p);
+    double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  }
+};
+template <> struct RawIO<double, 2> {
+  __device__ static void load(const double *p, double (&o)[2]) {
+    double2 a = *reinterpret_cast<const double2 *>(p);
+    o[0] = a.x; o[1] = a.y;
+  }
+};
+template <> struct RawIO<double, 1> {
+  __device__ static void load(const double *p, double (&o)[1]) { o[0] = *p; }
+};
+
 template <typename T> __device__ inline double round_to(double v) { return (double)(T)v; }
 
 __device__ inline double readlane_d(double v, int k) {
@@ -272,25 +306,44 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
         // first iteration of a solve, else min(d q, 1) = min(tau/||b||, 1)
         cl = (m > 0) ? fmin(dprev * a.qcsr[base + lane], 1.0) : 1.0 - a.s[a.eid[base + lane]];
       }
-      int k = 0;
-      for (; k + 8 <= cnt; k += 8) {
+      // Gathers in batches of 8 rows, two batches in flight: batch k+8 is
+      // issued before batch k is accumulated.
+      auto issue = [&](int k0, TG (&r)[8][VEC], double (&c)[8]) {
         int j[8];
-        double c[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) { j[q] = __builtin_amdgcn_readlane(jl, k + q); c[q] = readlane_d(cl, k + q); }
+        for (int q = 0; q < 8; ++q) { j[q] = __builtin_amdgcn_readlane(jl, k0 + q); c[q] = readlane_d(cl, k0 + q); }
+        if (active) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) RawIO<TG, VEC>::load(Gp + (size_t)j[q] * a.ld + f0, r[q]);
+        }
+      };
+      auto consume = [&](const TG (&r)[8][VEC], const double (&c)[8]) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) C += c[q];
         if (active) {
-          double xv[8][VEC];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) VecIO<VEC>::load(Gp + (size_t)j[q] * a.ld + f0, xv[q]);
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) { sumg[v] += xv[q][v]; sumcg[v] = fma(c[q], xv[q][v], sumcg[v]); }
+            for (int v = 0; v < VEC; ++v) {
+              const double xv = (double)r[q][v];
+              sumg[v] += xv;
+              sumcg[v] = fma(c[q], xv, sumcg[v]);
+            }
           }
         }
+      };
+      const int nfull = cnt & ~7;
+      TG ra[8][VEC], rb[8][VEC];
+      double ca[8], cb[8];
+      if (nfull > 0) issue(0, ra, ca);
+      for (int k0 = 0; k0 < nfull; k0 += 16) {
+        if (k0 + 8 < nfull) issue(k0 + 8, rb, cb);
+        consume(ra, ca);
+        if (k0 + 8 >= nfull) break;
+        if (k0 + 16 < nfull) issue(k0 + 16, ra, ca);
+        consume(rb, cb);
       }
+      int k = nfull;
       for (; k < cnt; ++k) {
         const int j0 = __builtin_amdgcn_readlane(jl, k);
         const double c0 = readlane_d(cl, k);
@@ -441,25 +494,23 @@ __device__ void finish_iteration(const double *psum, int nbp, const double *esum
   sc->m = m + 1;
 }
 
-// Block partials of the edge terms, then the last block to arrive finishes
-// the iteration.
-__device__ inline void edge_block_tail(double (&t3)[kEdgeSums], double *esum, const double *psum,
-                                       int nbp, double *trace, DevScalars *sc) {
-  __shared__ double red[kWavesPerBlock * (kPointSums + kEdgeSums)];
-  __shared__ int is_last;
+// Block partials of the edge terms (reduced in fixed order by k_finish).
+__device__ inline void edge_block_partials(double (&t3)[kEdgeSums], double *esum) {
+  __shared__ double red[kWavesPerBlock * kEdgeSums];
   block_sum<kEdgeSums>(t3, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < kEdgeSums; ++q) esum[(size_t)blockIdx.x * 4 + q] = t3[q];
-    __threadfence();
-    const unsigned prev = atomicAdd(&sc->counter, 1u);
-    is_last = (prev == gridDim.x - 1) ? 1 : 0;
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  finish_iteration(psum, nbp, esum, gridDim.x, trace, sc, red);
-  if (threadIdx.x == 0) sc->counter = 0u;
+}
+
+// One block: the end of an MM iteration.  Kernel boundaries order it after
+// every partial it reads, so no device-wide fences are needed.
+__global__ __launch_bounds__(kBlock) void k_finish(const double *psum, int nbp, const double *esum,
+                                                   int nbe, double *trace, DevScalars *sc) {
+  __shared__ double red[kWavesPerBlock * (kPointSums + kEdgeSums)];
+  if (sc->done) return;
+  finish_iteration(psum, nbp, esum, nbe, trace, sc, red);
 }
 
 // -------------------------------------------------------------- k_edge
@@ -520,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_edge(EdgeArgs a) {
     }
   }
   if (!FUSED || a.init) return;
-  edge_block_tail(t3, a.esum, a.psum, a.nbp, a.trace, sc);
+  edge_block_partials(t3, a.esum);
 }
 
 // ------------------------------------------------------- k_edge_reduce
@@ -537,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_reduce(ReduceArgs a) {
     edge_update(a.es, e, nb2, a.init, pa, sc, t3);
   }
   if (a.init) return;
-  edge_block_tail(t3, a.esum, a.psum, a.nbp, a.trace, sc);
+  edge_block_partials(t3, a.esum);
 }
 
 // --------------------------------------------------------- small kernels
@@ -762,8 +813,9 @@ static void launch_edge_t(Problem *P, int init, int nbp) {
   hipLaunchKernelGGL((k_edge<PREC, NPASS, FUSED>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea);
 }
 
+// Returns the number of blocks that wrote edge partials.
 template <int PREC>
-static void launch_edge_p(Problem *P, int init, int nbp) {
+static int launch_edge_p(Problem *P, int init, int nbp) {
   if (P->efused) {
     switch (P->npass) {
       case 1: launch_edge_t<PREC, 1, true>(P, init, nbp); break;
@@ -772,12 +824,13 @@ static void launch_edge_p(Problem *P, int init, int nbp) {
       case 8: launch_edge_t<PREC, 8, true>(P, init, nbp); break;
       default: launch_edge_t<PREC, 16, true>(P, init, nbp); break;
     }
-  } else {
-    launch_edge_t<PREC, 4, false>(P, init, nbp);
-    const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
-    ReduceArgs ra{P->entile, nbp, init, P->part, edge_state(P), P->esum, P->psum, P->trace, P->sc};
-    hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
+    return sweep_grid(P->n * P->entile).blocks;
   }
+  launch_edge_t<PREC, 4, false>(P, init, nbp);
+  const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
+  ReduceArgs ra{P->entile, nbp, init, P->part, edge_state(P), P->esum, P->psum, P->trace, P->sc};
+  hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
+  return rblocks;
 }
 
 template <int PREC>
@@ -797,22 +850,21 @@ static void launch_iteration(Problem *P) {
   else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
   else launch_point_p<kMixed>(P, Lp);
   if (ev) (void)hipEventRecord(ev[1], P->stream);
-  if (P->precision == kF32) launch_edge_p<kF32>(P, 0, Lp.blocks);
-  else if (P->precision == kF64) launch_edge_p<kF64>(P, 0, Lp.blocks);
-  else launch_edge_p<kMixed>(P, 0, Lp.blocks);
-  if (ev) {
-    // the fused edge kernel ends the iteration itself: the reduction slot
-    // then records zero time
-    (void)hipEventRecord(ev[2], P->stream);
-    (void)hipEventRecord(ev[3], P->stream);
-  }
+  int nbe;
+  if (P->precision == kF32) nbe = launch_edge_p<kF32>(P, 0, Lp.blocks);
+  else if (P->precision == kF64) nbe = launch_edge_p<kF64>(P, 0, Lp.blocks);
+  else nbe = launch_edge_p<kMixed>(P, 0, Lp.blocks);
+  if (ev) (void)hipEventRecord(ev[2], P->stream);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, P->stream, (const double *)P->psum,
+                     Lp.blocks, (const double *)P->esum, nbe, P->trace, P->sc);
+  if (ev) (void)hipEventRecord(ev[3], P->stream);
 }
 
 // Edge norms of the A in buffer pa (state set or reset).
 static void launch_edge_init(Problem *P) {
-  if (P->precision == kF32) launch_edge_p<kF32>(P, 1, 0);
-  else if (P->precision == kF64) launch_edge_p<kF64>(P, 1, 0);
-  else launch_edge_p<kMixed>(P, 1, 0);
+  if (P->precision == kF32) (void)launch_edge_p<kF32>(P, 1, 0);
+  else if (P->precision == kF64) (void)launch_edge_p<kF64>(P, 1, 0);
+  else (void)launch_edge_p<kMixed>(P, 1, 0);
 }
 
 cc_status profile(Problem *P, int32_t sample_every) {
