@@ -223,7 +223,7 @@ struct EdgeState {
 struct EdgeArgs {
   int n, ld, ntile, nitems, chunk, init, nbp;
   const void *G0, *G1;
-  const int32_t *rowptr, *uptr, *col, *eid;
+  const int32_t *ei, *ej;
   double *part;         // E x ntile partial ||b||^2 (ntile > 1)
   EdgeState es;
   double *esum;
@@ -415,25 +415,34 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
 }
 
 // --------------------------------------------------- per-edge bookkeeping
+// Per-edge inputs of the bookkeeping, loaded ahead of the row gathers.
+struct EdgeIn {
+  double qprev, nbprev, w, s;
+};
+
+__device__ inline EdgeIn edge_prefetch(const EdgeState &es, int e, int pa) {
+  const double *nbprev = pa == 0 ? es.nb0 : es.nb1;
+  return EdgeIn{es.qe[e], nbprev[e], es.w[e], es.s[e]};
+}
+
 // Given ||b_e||^2 of the new A_m: store ||b_e||; in an iteration also take
 // s_m (the shrink factor the point sweep used), accumulate the edge terms of
 // ||V - D A||^2 and of the penalty, and prepare q_e = mu w_e / (rho ||b_e||)
 // for the next point sweep (c = min(d q, 1) there, +inf when b_e = 0).
-__device__ inline void edge_update(const EdgeState &es, int e, double nb2, int init, int pa,
-                                   const DevScalars *sc, double (&t3)[kEdgeSums]) {
+__device__ inline void edge_update(const EdgeState &es, int e, double nb2, const EdgeIn &in, int init,
+                                   int pa, const DevScalars *sc, double (&t3)[kEdgeSums]) {
   double *nbout = init ? (pa == 0 ? es.nb0 : es.nb1) : (pa == 0 ? es.nb1 : es.nb0);
   const double nbn = sqrt(nb2);
   nbout[e] = nbn;
   if (init) return;
-  const double *nbprev = pa == 0 ? es.nb0 : es.nb1;
   const int m = sc->m;
-  const double sv = (m > 0) ? 1.0 - fmin(sc->d_prev * es.qe[e], 1.0) : es.s[e];
+  const double sv = (m > 0) ? 1.0 - fmin(sc->d_prev * in.qprev, 1.0) : in.s;
   es.s[e] = sv;
-  const double np = nbprev[e];
+  const double np = in.nbprev;
   t3[0] += nb2;
   t3[1] += (sv * np) * (sv * np);
-  t3[2] += es.w[e] * sv * np;
-  const double q = (nbn > 0.0) ? (sc->mu * es.w[e]) / (sc->rho * nbn) : __builtin_inf();
+  t3[2] += in.w * sv * np;
+  const double q = (nbn > 0.0) ? (sc->mu * in.w) / (sc->rho * nbn) : __builtin_inf();
   es.qe[e] = q;
   es.qcsr[es.epos[2 * e]] = q;
   es.qcsr[es.epos[2 * e + 1]] = q;
@@ -447,13 +456,34 @@ __device__ void finish_iteration(const double *psum, int nbp, const double *esum
   double v[kPointSums + kEdgeSums];
 #pragma unroll
   for (int q = 0; q < kPointSums + kEdgeSums; ++q) v[q] = 0.0;
-  for (int b = threadIdx.x; b < nbp; b += blockDim.x) {
+  // four rows per thread in flight, fixed order
+  for (int b0 = threadIdx.x; b0 < nbp; b0 += 4 * blockDim.x) {
+    double r[4][kPointSums];
 #pragma unroll
-    for (int q = 0; q < kPointSums; ++q) v[q] += psum[(size_t)b * 8 + q];
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * blockDim.x;
+#pragma unroll
+      for (int q = 0; q < kPointSums; ++q) r[u][q] = (b < nbp) ? psum[(size_t)b * 8 + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int q = 0; q < kPointSums; ++q) v[q] += r[u][q];
+    }
   }
-  for (int b = threadIdx.x; b < nbe; b += blockDim.x) {
+  for (int b0 = threadIdx.x; b0 < nbe; b0 += 4 * blockDim.x) {
+    double r[4][kEdgeSums];
 #pragma unroll
-    for (int q = 0; q < kEdgeSums; ++q) v[kPointSums + q] += esum[(size_t)b * 4 + q];
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * blockDim.x;
+#pragma unroll
+      for (int q = 0; q < kEdgeSums; ++q) r[u][q] = (b < nbe) ? esum[(size_t)b * 4 + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int q = 0; q < kEdgeSums; ++q) v[kPointSums + q] += r[u][q];
+    }
   }
   block_sum<kPointSums + kEdgeSums>(v, red);
   if (threadIdx.x != 0) return;
@@ -506,18 +536,19 @@ __device__ inline void edge_block_partials(double (&t3)[kEdgeSums], double *esum
 
 // One block: the end of an MM iteration.  Kernel boundaries order it after
 // every partial it reads, so no device-wide fences are needed.
-__global__ __launch_bounds__(kBlock) void k_finish(const double *psum, int nbp, const double *esum,
-                                                   int nbe, double *trace, DevScalars *sc) {
-  __shared__ double red[kWavesPerBlock * (kPointSums + kEdgeSums)];
+__global__ __launch_bounds__(1024) void k_finish(const double *psum, int nbp, const double *esum,
+                                                 int nbe, double *trace, DevScalars *sc) {
+  __shared__ double red[16 * (kPointSums + kEdgeSums)];
   if (sc->done) return;
   finish_iteration(psum, nbp, esum, nbe, trace, sc, red);
 }
 
 // -------------------------------------------------------------- k_edge
-// One wave per (point i, tile); each quarter-wave takes one upper neighbour
-// j > i and sums (a_i - a_j)^2 over the tile, 4 features per lane per pass.
-// FUSED (one tile covers the row): the quarter leader finishes the edge and
-// the kernel ends the iteration; otherwise per-tile partials are written.
+// Edge-parallel: a work item is a group of 4 consecutive edges (one per
+// quarter-wave) in one feature tile; each quarter sums (a_i - a_j)^2 over the
+// tile, 4 features per lane per pass, then reduces over its 16 lanes.
+// FUSED (one tile covers the row): the quarter leader finishes the edge;
+// otherwise per-tile partials are written for k_edge_reduce.
 template <int PREC, int NPASS, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_edge(EdgeArgs a) {
   using TG = typename Traits<PREC>::TG;
@@ -533,41 +564,55 @@ __global__ __launch_bounds__(kBlock) void k_edge(EdgeArgs a) {
   const int lb = logical_block();
   const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
   const int W = 64 * NPASS;
+  const int ngroups = (a.es.E + 3) / 4;
   double t3[kEdgeSums] = {0.0, 0.0, 0.0};
   for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
-    const int t = item / a.n, i = item - t * a.n;
-    double gi[NPASS][4];
-#pragma unroll
-    for (int ps = 0; ps < NPASS; ++ps) {
-      const int fo = t * W + ps * 64 + l16 * 4;
-      if (fo < a.ld) VecIO<4>::load(Gc + (size_t)i * a.ld + fo, gi[ps]);
-      else { gi[ps][0] = gi[ps][1] = gi[ps][2] = gi[ps][3] = 0.0; }
+    const int t = item / ngroups, g = item - t * ngroups;
+    const int e = 4 * g + q;
+    const bool valid = e < a.es.E;
+    int i = 0, j = 0;
+    EdgeIn in{0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+      i = a.ei[e];
+      j = a.ej[e];
+      if (FUSED && !a.init) in = edge_prefetch(a.es, e, pa);
     }
-    const int us = a.uptr[i], re = a.rowptr[i + 1];
-    for (int k = us; k < re; k += 4) {
-      const int kk = k + q;
-      const bool valid = kk < re;
-      int j = i, e = 0;
-      if (valid) { j = a.col[kk]; e = a.eid[kk]; }
-      double acc = 0.0;
+    double acc = 0.0;
+    // two rows per edge: load both tiles, then accumulate
+    if (valid) {
+      // groups of up to 4 passes: 8 row loads in flight per lane
+      constexpr int PG = NPASS < 4 ? NPASS : 4;
+#pragma unroll 1
+      for (int pg = 0; pg < NPASS; pg += PG) {
+        TG ri[PG][4], rj[PG][4];
 #pragma unroll
-      for (int ps = 0; ps < NPASS; ++ps) {
-        const int fo = t * W + ps * 64 + l16 * 4;
-        if (valid && fo < a.ld) {
-          double xj[4];
-          VecIO<4>::load(Gc + (size_t)j * a.ld + fo, xj);
+        for (int ps = 0; ps < PG; ++ps) {
+          const int fo = t * W + (pg + ps) * 64 + l16 * 4;
+          if (fo < a.ld) {
+            RawIO<TG, 4>::load(Gc + (size_t)i * a.ld + fo, ri[ps]);
+            RawIO<TG, 4>::load(Gc + (size_t)j * a.ld + fo, rj[ps]);
+          } else {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) { const double d = gi[ps][v] - xj[v]; acc = fma(d, d, acc); }
+            for (int v = 0; v < 4; ++v) ri[ps][v] = rj[ps][v] = (TG)0;
+          }
+        }
+#pragma unroll
+        for (int ps = 0; ps < PG; ++ps) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double d = (double)ri[ps][v] - (double)rj[ps][v];
+            acc = fma(d, d, acc);
+          }
         }
       }
-      acc += __shfl_xor(acc, 8, kWave);
-      acc += __shfl_xor(acc, 4, kWave);
-      acc += __shfl_xor(acc, 2, kWave);
-      acc += __shfl_xor(acc, 1, kWave);
-      if (valid && l16 == 0) {
-        if (FUSED) edge_update(a.es, e, acc, a.init, pa, sc, t3);
-        else a.part[(size_t)e * a.ntile + t] = acc;
-      }
+    }
+    acc += __shfl_xor(acc, 8, kWave);
+    acc += __shfl_xor(acc, 4, kWave);
+    acc += __shfl_xor(acc, 2, kWave);
+    acc += __shfl_xor(acc, 1, kWave);
+    if (valid && l16 == 0) {
+      if (FUSED) edge_update(a.es, e, acc, in, a.init, pa, sc, t3);
+      else a.part[(size_t)e * a.ntile + t] = acc;
     }
   }
   if (!FUSED || a.init) return;
@@ -584,8 +629,10 @@ __global__ __launch_bounds__(kBlock) void k_edge_reduce(ReduceArgs a) {
   double t3[kEdgeSums] = {0.0, 0.0, 0.0};
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < a.es.E; e += gridDim.x * blockDim.x) {
     double nb2 = 0.0;
+    EdgeIn in{0.0, 0.0, 0.0, 0.0};
+    if (!a.init) in = edge_prefetch(a.es, e, pa);
     for (int t = 0; t < a.ntile; ++t) nb2 += a.part[(size_t)e * a.ntile + t];
-    edge_update(a.es, e, nb2, a.init, pa, sc, t3);
+    edge_update(a.es, e, nb2, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
   edge_block_partials(t3, a.esum);
@@ -806,9 +853,9 @@ static EdgeState edge_state(Problem *P) {
 
 template <int PREC, int NPASS, bool FUSED>
 static void launch_edge_t(Problem *P, int init, int nbp) {
-  const Launch Le = sweep_grid(P->n * P->entile);
+  const Launch Le = sweep_grid(cdiv(P->E, 4) * P->entile);
   EdgeArgs ea{(int)P->n, (int)P->ld, P->entile, Le.nitems, Le.chunk, init, nbp,
-              P->G[0], P->G[1], P->rowptr, P->uptr, P->col, P->eid, P->part,
+              P->G[0], P->G[1], P->ei, P->ej, P->part,
               edge_state(P), P->esum, P->psum, P->trace, P->sc};
   hipLaunchKernelGGL((k_edge<PREC, NPASS, FUSED>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea);
 }
@@ -824,7 +871,7 @@ static int launch_edge_p(Problem *P, int init, int nbp) {
       case 8: launch_edge_t<PREC, 8, true>(P, init, nbp); break;
       default: launch_edge_t<PREC, 16, true>(P, init, nbp); break;
     }
-    return sweep_grid(P->n * P->entile).blocks;
+    return sweep_grid(cdiv(P->E, 4) * P->entile).blocks;
   }
   launch_edge_t<PREC, 4, false>(P, init, nbp);
   const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
@@ -855,7 +902,7 @@ static void launch_iteration(Problem *P) {
   else if (P->precision == kF64) nbe = launch_edge_p<kF64>(P, 0, Lp.blocks);
   else nbe = launch_edge_p<kMixed>(P, 0, Lp.blocks);
   if (ev) (void)hipEventRecord(ev[2], P->stream);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(kBlock), 0, P->stream, (const double *)P->psum,
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, P->stream, (const double *)P->psum,
                      Lp.blocks, (const double *)P->esum, nbe, P->trace, P->sc);
   if (ev) (void)hipEventRecord(ev[3], P->stream);
 }
