@@ -60,8 +60,15 @@ struct Problem {
   int32_t *rowptr = nullptr, *col = nullptr, *eid = nullptr, *uptr = nullptr;
   int32_t *ei = nullptr, *ej = nullptr;
   double *w = nullptr, *s = nullptr, *nb[2] = {nullptr, nullptr};
-  double *qe = nullptr, *qcsr = nullptr;  // mu w / (rho ||b||), per edge and per CSR entry
-  int32_t *epos = nullptr;                // CSR positions of both directions of each edge
+  double *qe = nullptr;     // mu w / (rho ||b||) per edge
+  // point-sweep neighbour lists, fixed stride ell_s per point (ELL layout):
+  // entries i*ell_s .. i*ell_s + degE[i] - 1 hold the neighbours of i
+  int ell_s = 1;
+  int32_t *degE = nullptr, *colE = nullptr, *eidE = nullptr;
+  double *qE = nullptr;     // q per ELL entry
+  int32_t *epos = nullptr;  // ELL positions of (i->j) and (j->i) per edge
+  double cur_rho = 1.0;     // constants of the solve in progress
+  int cur_K = 64;
   double *part = nullptr;    // E x entile edge partials
   double *psum = nullptr;    // kMaxBlocks x 8 point partials
   double *esum = nullptr;    // kMaxBlocks x 4 edge partials

@@ -201,9 +201,12 @@ struct PointArgs {
   void *U;
   void *A0, *A1, *G0, *G1;
   void *Usnap, *Asnap;
-  const int32_t *rowptr, *col, *eid;
-  const double *qcsr;   // mu w / (rho ||b||) of the previous A, per CSR entry
+  int ell_s;            // ELL stride of the neighbour lists
+  const int32_t *degE, *colE, *eidE;
+  const double *qE;     // mu w / (rho ||b||) of the previous A, per ELL entry
   const double *s;      // state shrink factors (first iteration of a solve)
+  double rho;           // constants of the solve
+  int K;
   double *psum;
   DevScalars *sc;
 };
@@ -216,14 +219,15 @@ struct EdgeState {
   double *s;            // s_m written here (the state's V factors)
   double *nb0, *nb1;    // ||b|| per edge, double-buffered with A
   double *qe;           // q per edge
-  double *qcsr;         // q per CSR entry (both directions)
-  const int32_t *epos;  // CSR positions of (i->j) and (j->i) per edge
+  double *qE;           // q per ELL entry (both directions)
+  const int32_t *epos;  // ELL positions of (i->j) and (j->i) per edge
 };
 
 struct EdgeArgs {
   int n, ld, ntile, nitems, chunk, init, nbp;
   const void *G0, *G1;
   const int32_t *ei, *ej;
+  const int32_t *rowptr, *uptr, *col, *eid;  // CSR (wide-row tiles)
   double *part;         // E x ntile partial ||b||^2 (ntile > 1)
   EdgeState es;
   double *esum;
@@ -252,11 +256,11 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
   DevScalars *sc = a.sc;
   if (sc->done) return;
   const int m = sc->m, pa = sc->pa;
-  const double rho = sc->rho, dprev = sc->d_prev;
+  const double rho = a.rho, dprev = sc->d_prev;
   const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
   // stop-test window: U snapshots at m = 0, K, 2K, ...; A snapshots at
   // m = K-1, 2K-1, ... (the start-of-solve A' seeds the first A window)
-  const int K = sc->K;
+  const int K = a.K;
   const bool snapU0 = (m == 0), winU = (m > 0) && (m % K == 0);
   const bool initA = (m == 0) && (K > 1), winA = (m % K) == (K - 1);
   TS *Us = reinterpret_cast<TS *>(a.Usnap);
@@ -280,8 +284,9 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
     const int f0 = t * W + lane * VEC;
     const bool active = f0 < a.ld;
     const size_t row = (size_t)i * a.ld + f0;
-    const int rs = a.rowptr[i], re = a.rowptr[i + 1];
-    const int deg = re - rs;
+    const int rs = i * a.ell_s;
+    const int deg = a.degE[i];
+    const int re = rs + deg;
 
     double gi[VEC], ap[VEC], up[VEC], x[VEC];
     bool mk[VEC];
@@ -301,10 +306,10 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
       int jl = 0;
       double cl = 0.0;
       if (lane < cnt) {
-        jl = a.col[base + lane];
+        jl = a.colE[base + lane];
         // c = 1 - s with s the V-update shrink factor; from the state at the
         // first iteration of a solve, else min(d q, 1) = min(tau/||b||, 1)
-        cl = (m > 0) ? fmin(dprev * a.qcsr[base + lane], 1.0) : 1.0 - a.s[a.eid[base + lane]];
+        cl = (m > 0) ? fmin(dprev * a.qE[base + lane], 1.0) : 1.0 - a.s[a.eidE[base + lane]];
       }
       // Gathers in batches of 8 rows, two batches in flight: batch k+8 is
       // issued before batch k is accumulated.
@@ -421,8 +426,9 @@ struct EdgeIn {
 };
 
 __device__ inline EdgeIn edge_prefetch(const EdgeState &es, int e, int pa) {
-  const double *nbprev = pa == 0 ? es.nb0 : es.nb1;
-  return EdgeIn{es.qe[e], nbprev[e], es.w[e], es.s[e]};
+  // both norm buffers are read so that the loads do not wait on pa
+  const double n0 = es.nb0[e], n1 = es.nb1[e];
+  return EdgeIn{es.qe[e], pa == 0 ? n0 : n1, es.w[e], es.s[e]};
 }
 
 // Given ||b_e||^2 of the new A_m: store ||b_e||; in an iteration also take
@@ -444,19 +450,20 @@ __device__ inline void edge_update(const EdgeState &es, int e, double nb2, const
   t3[2] += in.w * sv * np;
   const double q = (nbn > 0.0) ? (sc->mu * in.w) / (sc->rho * nbn) : __builtin_inf();
   es.qe[e] = q;
-  es.qcsr[es.epos[2 * e]] = q;
-  es.qcsr[es.epos[2 * e + 1]] = q;
+  es.qE[es.epos[2 * e]] = q;
+  es.qE[es.epos[2 * e + 1]] = q;
 }
 
 // ------------------------------------------------------- iteration finish
 // Fixed-order sums of every point and edge partial, then d, the objective,
-// the windowed stop test and the advance of the iteration scalars.
+// the windowed stop test and the advance of the iteration scalars.  All
+// loads (scalars and partials) are issued before anything waits on them.
 __device__ void finish_iteration(const double *psum, int nbp, const double *esum, int nbe,
                                  double *trace, DevScalars *sc, double *red) {
+  const DevScalars h = *sc;  // snapshot of the iteration scalars
   double v[kPointSums + kEdgeSums];
 #pragma unroll
   for (int q = 0; q < kPointSums + kEdgeSums; ++q) v[q] = 0.0;
-  // four rows per thread in flight, fixed order
   for (int b0 = threadIdx.x; b0 < nbp; b0 += 4 * blockDim.x) {
     double r[4][kPointSums];
 #pragma unroll
@@ -485,34 +492,35 @@ __device__ void finish_iteration(const double *psum, int nbp, const double *esum
       for (int q = 0; q < kEdgeSums; ++q) v[kPointSums + q] += r[u][q];
     }
   }
+  if (h.done) return;  // uniform
   block_sum<kPointSums + kEdgeSums>(v, red);
   if (threadIdx.x != 0) return;
   const double uA2 = v[0], dAw = v[1], dUw = v[2], loss2 = v[3], u2 = v[4], cross = v[5];
   const double Cs = v[6], As = v[7], pen = v[8];
   const double viol = fmax(As - 2.0 * cross + Cs, 0.0);
-  const double d = sqrt(uA2 + viol + sc->eps);
-  const double F = 0.5 * loss2 + sc->mu * pen + sc->rho * d;
-  const int m = sc->m;
-  if (sc->record && trace) trace[m] = F;
+  const double d = sqrt(uA2 + viol + h.eps);
+  const double F = 0.5 * loss2 + h.mu * pen + h.rho * d;
+  const int m = h.m;
+  if (h.record && trace) trace[m] = F;
   if (!isfinite(d) || !isfinite(F)) {
     sc->status = CC_ERR_NUMERIC; sc->done = 1; sc->iters = m;
     return;
   }
-  const int K = sc->K;
+  const int K = h.K;
   if (m >= 1) {
     // iteration m-1 of the MM loop has now finished
-    sc->F_last = sc->F_cur;
-    sc->d_last = sc->d_prev;
+    sc->F_last = h.F_cur;
+    sc->d_last = h.d_prev;
     if (m % K == 0) {
-      const double r = sqrt(dUw + sc->dA_prev) / (double)K;
+      const double r = sqrt(dUw + h.dA_prev) / (double)K;
       const double unorm = fmax(1.0, sqrt(u2));
       sc->rel_last = r / unorm;
-      if (sc->thr > 0.0 && m - 1 >= 2 && r <= sc->thr * unorm) {
+      if (h.thr > 0.0 && m - 1 >= 2 && r <= h.thr * unorm) {
         sc->done = 1; sc->converged = 1; sc->iters = m;
         return;
       }
     }
-    if (m >= sc->max_iter) {
+    if (m >= h.max_iter) {
       sc->done = 1; sc->converged = 0; sc->iters = m;
       return;
     }
@@ -520,7 +528,7 @@ __device__ void finish_iteration(const double *psum, int nbp, const double *esum
   sc->F_cur = F;
   sc->d_prev = d;
   if (m % K == K - 1) sc->dA_prev = dAw;
-  sc->pa ^= 1;
+  sc->pa = h.pa ^ 1;
   sc->m = m + 1;
 }
 
@@ -539,55 +547,49 @@ __device__ inline void edge_block_partials(double (&t3)[kEdgeSums], double *esum
 __global__ __launch_bounds__(1024) void k_finish(const double *psum, int nbp, const double *esum,
                                                  int nbe, double *trace, DevScalars *sc) {
   __shared__ double red[16 * (kPointSums + kEdgeSums)];
-  if (sc->done) return;
   finish_iteration(psum, nbp, esum, nbe, trace, sc, red);
 }
 
 // -------------------------------------------------------------- k_edge
-// Edge-parallel: a work item is a group of 4 consecutive edges (one per
-// quarter-wave) in one feature tile; each quarter sums (a_i - a_j)^2 over the
-// tile, 4 features per lane per pass, then reduces over its 16 lanes.
-// FUSED (one tile covers the row): the quarter leader finishes the edge;
-// otherwise per-tile partials are written for k_edge_reduce.
-template <int PREC, int NPASS, bool FUSED>
-__global__ __launch_bounds__(kBlock) void k_edge(EdgeArgs a) {
+// Rows up to 1024 wide: edge-parallel.  A work item is a group of 4
+// consecutive edges (one per quarter-wave); each quarter sums (a_i - a_j)^2
+// over the row, 4 features per lane per 64-feature pass, reduces over its 16
+// lanes, and the quarter leader finishes the edge.
+template <int PREC, int NPASS>
+__global__ __launch_bounds__(kBlock) void k_edge_fused(EdgeArgs a) {
   using TG = typename Traits<PREC>::TG;
   DevScalars *sc = a.sc;
-  if (!a.init && sc->done) return;
-  const int pa = sc->pa;
-  // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
-  const int buf = a.init ? pa : (pa ^ 1);
-  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int q = lane / 16, l16 = lane % 16;
   const int lb = logical_block();
   const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
-  const int W = 64 * NPASS;
-  const int ngroups = (a.es.E + 3) / 4;
+  if (!a.init && sc->done) return;
+  const int pa = sc->pa;
+  // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
+  const int buf = a.init ? pa : (pa ^ 1);
+  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
   double t3[kEdgeSums] = {0.0, 0.0, 0.0};
   for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
-    const int t = item / ngroups, g = item - t * ngroups;
-    const int e = 4 * g + q;
+    const int e = 4 * item + q;
     const bool valid = e < a.es.E;
     int i = 0, j = 0;
     EdgeIn in{0.0, 0.0, 0.0, 0.0};
     if (valid) {
       i = a.ei[e];
       j = a.ej[e];
-      if (FUSED && !a.init) in = edge_prefetch(a.es, e, pa);
+      if (!a.init) in = edge_prefetch(a.es, e, pa);
     }
     double acc = 0.0;
-    // two rows per edge: load both tiles, then accumulate
     if (valid) {
       // groups of up to 4 passes: 8 row loads in flight per lane
       constexpr int PG = NPASS < 4 ? NPASS : 4;
-#pragma unroll 1
+#pragma unroll
       for (int pg = 0; pg < NPASS; pg += PG) {
         TG ri[PG][4], rj[PG][4];
 #pragma unroll
         for (int ps = 0; ps < PG; ++ps) {
-          const int fo = t * W + (pg + ps) * 64 + l16 * 4;
+          const int fo = (pg + ps) * 64 + l16 * 4;
           if (fo < a.ld) {
             RawIO<TG, 4>::load(Gc + (size_t)i * a.ld + fo, ri[ps]);
             RawIO<TG, 4>::load(Gc + (size_t)j * a.ld + fo, rj[ps]);
@@ -610,13 +612,70 @@ __global__ __launch_bounds__(kBlock) void k_edge(EdgeArgs a) {
     acc += __shfl_xor(acc, 4, kWave);
     acc += __shfl_xor(acc, 2, kWave);
     acc += __shfl_xor(acc, 1, kWave);
-    if (valid && l16 == 0) {
-      if (FUSED) edge_update(a.es, e, acc, in, a.init, pa, sc, t3);
-      else a.part[(size_t)e * a.ntile + t] = acc;
+    if (valid && l16 == 0) edge_update(a.es, e, acc, in, a.init, pa, sc, t3);
+  }
+  if (a.init) return;
+  edge_block_partials(t3, a.esum);
+}
+
+// Wide rows: one wave per (point i, 256-feature tile); each quarter-wave
+// takes one upper neighbour j > i (so a_i is read once per point and tile)
+// and writes the tile's partial (a_i - a_j)^2 for k_edge_reduce.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_edge_tiles(EdgeArgs a) {
+  using TG = typename Traits<PREC>::TG;
+  constexpr int NPASS = 4;
+  DevScalars *sc = a.sc;
+  if (!a.init && sc->done) return;
+  const int pa = sc->pa;
+  const int buf = a.init ? pa : (pa ^ 1);
+  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int q = lane / 16, l16 = lane % 16;
+  const int lb = logical_block();
+  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
+  const int W = 64 * NPASS;
+  for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
+    const int t = item / a.n, i = item - t * a.n;
+    double gi[NPASS][4];
+#pragma unroll
+    for (int ps = 0; ps < NPASS; ++ps) {
+      const int fo = t * W + ps * 64 + l16 * 4;
+      if (fo < a.ld) VecIO<4>::load(Gc + (size_t)i * a.ld + fo, gi[ps]);
+      else { gi[ps][0] = gi[ps][1] = gi[ps][2] = gi[ps][3] = 0.0; }
+    }
+    const int us = a.uptr[i], re = a.rowptr[i + 1];
+    for (int k = us; k < re; k += 4) {
+      const int kk = k + q;
+      const bool valid = kk < re;
+      int j = i, e = 0;
+      if (valid) { j = a.col[kk]; e = a.eid[kk]; }
+      double acc = 0.0;
+      if (valid) {
+        TG rj[NPASS][4];
+#pragma unroll
+        for (int ps = 0; ps < NPASS; ++ps) {
+          const int fo = t * W + ps * 64 + l16 * 4;
+          if (fo < a.ld) RawIO<TG, 4>::load(Gc + (size_t)j * a.ld + fo, rj[ps]);
+          else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) rj[ps][v] = (TG)0;
+          }
+        }
+#pragma unroll
+        for (int ps = 0; ps < NPASS; ++ps) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) { const double d = gi[ps][v] - (double)rj[ps][v]; acc = fma(d, d, acc); }
+        }
+      }
+      acc += __shfl_xor(acc, 8, kWave);
+      acc += __shfl_xor(acc, 4, kWave);
+      acc += __shfl_xor(acc, 2, kWave);
+      acc += __shfl_xor(acc, 1, kWave);
+      if (valid && l16 == 0) a.part[(size_t)e * a.ntile + t] = acc;
     }
   }
-  if (!FUSED || a.init) return;
-  edge_block_partials(t3, a.esum);
 }
 
 // ------------------------------------------------------- k_edge_reduce
@@ -843,37 +902,39 @@ template <int PREC, int VEC>
 static void launch_point_t(Problem *P, const Launch &Lp) {
   PointArgs pa{(int)P->n, (int)P->ld, P->ntile, Lp.nitems, Lp.chunk,
                P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
-               P->rowptr, P->col, P->eid, P->qcsr, P->s, P->psum, P->sc};
+               P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_rho, P->cur_K,
+               P->psum, P->sc};
   hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kBlock), 0, P->stream, pa);
 }
 
 static EdgeState edge_state(Problem *P) {
-  return EdgeState{(int)P->E, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qcsr, P->epos};
+  return EdgeState{(int)P->E, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qE, P->epos};
 }
 
-template <int PREC, int NPASS, bool FUSED>
-static void launch_edge_t(Problem *P, int init, int nbp) {
-  const Launch Le = sweep_grid(cdiv(P->E, 4) * P->entile);
-  EdgeArgs ea{(int)P->n, (int)P->ld, P->entile, Le.nitems, Le.chunk, init, nbp,
-              P->G[0], P->G[1], P->ei, P->ej, P->part,
-              edge_state(P), P->esum, P->psum, P->trace, P->sc};
-  hipLaunchKernelGGL((k_edge<PREC, NPASS, FUSED>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea);
+static EdgeArgs edge_args(Problem *P, const Launch &Le, int init, int nbp) {
+  return EdgeArgs{(int)P->n, (int)P->ld, P->entile, Le.nitems, Le.chunk, init, nbp,
+                  P->G[0], P->G[1], P->ei, P->ej, P->rowptr, P->uptr, P->col, P->eid, P->part,
+                  edge_state(P), P->esum, P->psum, P->trace, P->sc};
 }
 
 // Returns the number of blocks that wrote edge partials.
 template <int PREC>
 static int launch_edge_p(Problem *P, int init, int nbp) {
   if (P->efused) {
+    const Launch Le = sweep_grid(cdiv(P->E, 4));
+    const EdgeArgs ea = edge_args(P, Le, init, nbp);
     switch (P->npass) {
-      case 1: launch_edge_t<PREC, 1, true>(P, init, nbp); break;
-      case 2: launch_edge_t<PREC, 2, true>(P, init, nbp); break;
-      case 4: launch_edge_t<PREC, 4, true>(P, init, nbp); break;
-      case 8: launch_edge_t<PREC, 8, true>(P, init, nbp); break;
-      default: launch_edge_t<PREC, 16, true>(P, init, nbp); break;
+      case 1: hipLaunchKernelGGL((k_edge_fused<PREC, 1>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
+      case 2: hipLaunchKernelGGL((k_edge_fused<PREC, 2>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
+      case 4: hipLaunchKernelGGL((k_edge_fused<PREC, 4>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
+      case 8: hipLaunchKernelGGL((k_edge_fused<PREC, 8>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
+      default: hipLaunchKernelGGL((k_edge_fused<PREC, 16>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
     }
-    return sweep_grid(cdiv(P->E, 4) * P->entile).blocks;
+    return Le.blocks;
   }
-  launch_edge_t<PREC, 4, false>(P, init, nbp);
+  const Launch Le = sweep_grid(P->n * P->entile);
+  hipLaunchKernelGGL((k_edge_tiles<PREC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream,
+                     edge_args(P, Le, init, nbp));
   const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
   ReduceArgs ra{P->entile, nbp, init, P->part, edge_state(P), P->esum, P->psum, P->trace, P->sc};
   hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
@@ -943,7 +1004,8 @@ cc_status harvest_profile(Problem *P) {
 void problem_free(Problem *P) {
   if (!P) return;
   void *bufs[] = {P->X, P->M, P->U, P->A[0], P->A[1], P->Usnap, P->Asnap, P->rowptr, P->col, P->eid, P->uptr,
-                  P->ei, P->ej, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qcsr, P->epos, P->part, P->psum,
+                  P->ei, P->ej, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qE, P->epos, P->degE, P->colE,
+                  P->eidE, P->part, P->psum,
                   P->esum, P->trace, P->sc, P->ncl_dev};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -1079,7 +1141,6 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   CC_TRY(dmalloc((void **)&P->nb[0], E * 8));
   CC_TRY(dmalloc((void **)&P->nb[1], E * 8));
   CC_TRY(dmalloc((void **)&P->qe, E * 8));
-  CC_TRY(dmalloc((void **)&P->qcsr, 2 * E * 8));
   CC_TRY(dmalloc((void **)&P->epos, 2 * E * 4));
   CC_TRY(dmalloc((void **)&P->part, E * (P->efused ? 1 : P->entile) * 8));
   CC_TRY(dmalloc((void **)&P->psum, kMaxBlocks * 8 * 8));
@@ -1117,12 +1178,38 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
     maxdeg = std::max<int64_t>(maxdeg, rp[i + 1] - rp[i]);
   }
   P->max_deg = maxdeg;
+  // ELL copy of the neighbour lists for the point sweep
+  const int64_t S = std::max<int64_t>(maxdeg, 1);
+  P->ell_s = (int)S;
+  std::vector<int32_t> hdegE(n), hcolE(n * S, 0), heidE(n * S, 0), hposE(2 * E);
+  for (int64_t i = 0; i < n; ++i) {
+    hdegE[i] = rp[i + 1] - rp[i];
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int64_t slot = i * S + (k - rp[i]);
+      hcolE[slot] = hcol[k];
+      heidE[slot] = heid[k];
+    }
+  }
+  for (int64_t e2 = 0; e2 < 2 * E; ++e2) {
+    // hpos holds CSR positions; map them to ELL slots
+    const int32_t k = hpos[e2];
+    const int64_t row = (e2 % 2 == 0) ? hi[e2 / 2] : hj[e2 / 2];
+    hposE[e2] = (int32_t)(row * S + (k - rp[row]));
+  }
+  if ((int64_t)n * S > ((int64_t)1 << 31) - 1) { set_error("neighbour lists too large"); return CC_ERR_INVALID_ARG; }
+  CC_TRY(dmalloc((void **)&P->degE, n * 4));
+  CC_TRY(dmalloc((void **)&P->colE, n * S * 4));
+  CC_TRY(dmalloc((void **)&P->eidE, n * S * 4));
+  CC_TRY(dmalloc((void **)&P->qE, n * S * 8));
+  CC_HIP(hipMemcpyAsync(P->degE, hdegE.data(), n * 4, hipMemcpyHostToDevice, stream));
+  CC_HIP(hipMemcpyAsync(P->colE, hcolE.data(), n * S * 4, hipMemcpyHostToDevice, stream));
+  CC_HIP(hipMemcpyAsync(P->eidE, heidE.data(), n * S * 4, hipMemcpyHostToDevice, stream));
   CC_HIP(hipMemcpyAsync(P->rowptr, rp.data(), (n + 1) * 4, hipMemcpyHostToDevice, stream));
   CC_HIP(hipMemcpyAsync(P->uptr, hup.data(), n * 4, hipMemcpyHostToDevice, stream));
   if (E > 0) {
     CC_HIP(hipMemcpyAsync(P->col, hcol.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
     CC_HIP(hipMemcpyAsync(P->eid, heid.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
-    CC_HIP(hipMemcpyAsync(P->epos, hpos.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
+    CC_HIP(hipMemcpyAsync(P->epos, hposE.data(), 2 * E * 4, hipMemcpyHostToDevice, stream));
     CC_HIP(hipMemcpyAsync(P->ei, hi.data(), E * 4, hipMemcpyHostToDevice, stream));
     CC_HIP(hipMemcpyAsync(P->ej, hj.data(), E * 4, hipMemcpyHostToDevice, stream));
     CC_HIP(hipMemcpyAsync(P->w, hw.data(), E * 8, hipMemcpyHostToDevice, stream));
@@ -1233,6 +1320,8 @@ cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info 
   const double eps = o.eps > 0 ? o.eps : (o.eta * rho) * (o.eta * rho);
   const double eta = std::sqrt(eps) / rho;
   const double thr = o.tol > 0 ? o.tol * eta : 0.0;
+  P->cur_rho = rho;
+  P->cur_K = o.test_every;
   if (o.record_objective) {
     const int64_t need = (int64_t)o.max_iter + 2;
     if (P->trace_cap < need) {
