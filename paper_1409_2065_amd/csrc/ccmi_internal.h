@@ -67,6 +67,8 @@ struct Problem {
   int32_t *degE = nullptr, *colE = nullptr, *eidE = nullptr;
   double *qE = nullptr;     // q per ELL entry
   int32_t *epos = nullptr;  // ELL positions of (i->j) and (j->i) per edge
+  int slab_f = 0;           // > 0: LDS-slab point sweep with F-feature tiles
+  bool ell_cm = false;      // ELL stored column-major (entry k of i at k*n + i)
   double cur_rho = 1.0;     // constants of the solve in progress
   int cur_K = 64;
   double *part = nullptr;    // E x entile edge partials

@@ -419,6 +419,164 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
   }
 }
 
+// ------------------------------------------------------- k_point_slab
+// Narrow problems, where an n x F tile of the gather copy fits in LDS: one
+// block per (F-feature tile, 256 points).  The block stages the tile of A'
+// for all n points in LDS once; each lane owns one point, walks its
+// neighbour list (column-major ELL: entry k of point i at k*n + i, so the
+// lanes of a wave read consecutive entries) and gathers neighbour rows from
+// LDS instead of L2.  Same arithmetic as k_point.
+template <int PREC, int F>
+__global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
+  using TS = typename Traits<PREC>::TS;
+  using TG = typename Traits<PREC>::TG;
+  using TX = typename Traits<PREC>::TX;
+  constexpr int C4 = F / 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  TG *slab = reinterpret_cast<TG *>(smem);
+  __shared__ double scratch[kWavesPerBlock * kPointSums];
+  DevScalars *sc = a.sc;
+  if (sc->done) return;
+  const int m = sc->m, pa = sc->pa;
+  const double rho = a.rho, dprev = sc->d_prev;
+  const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
+  const int K = a.K;
+  const bool snapU0 = (m == 0), winU = (m > 0) && (m % K == 0);
+  const bool initA = (m == 0) && (K > 1), winA = (m % K) == (K - 1);
+  TS *Us = reinterpret_cast<TS *>(a.Usnap);
+  TS *As = reinterpret_cast<TS *>(a.Asnap);
+  const TS *Ap = reinterpret_cast<const TS *>(pa == 0 ? a.A0 : a.A1);
+  TS *An = reinterpret_cast<TS *>(pa == 0 ? a.A1 : a.A0);
+  const TG *Gp = reinterpret_cast<const TG *>(pa == 0 ? a.G0 : a.G1);
+  TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
+  const TX *X = reinterpret_cast<const TX *>(a.X);
+  TS *U = reinterpret_cast<TS *>(a.U);
+
+  const int lb = logical_block();
+  const int npg = (a.n + kBlock - 1) / kBlock;
+  const int t = lb / npg, g = lb - t * npg;
+  double ps[kPointSums] = {0, 0, 0, 0, 0, 0};
+  if (t < a.ntile) {
+    const int fbase = t * F;
+    // stage the tile of A' (gather copy) for every point
+    for (int idx = threadIdx.x; idx < a.n * C4; idx += blockDim.x) {
+      const int row = idx / C4, c = idx - row * C4;
+      const int f = fbase + 4 * c;
+      TG v[4] = {(TG)0, (TG)0, (TG)0, (TG)0};
+      if (f < a.ld) RawIO<TG, 4>::load(Gp + (size_t)row * a.ld + f, v);
+      TG *dst = slab + (size_t)row * F + 4 * c;
+      dst[0] = v[0]; dst[1] = v[1]; dst[2] = v[2]; dst[3] = v[3];
+    }
+    __syncthreads();
+    const int i = g * kBlock + threadIdx.x;
+    if (i < a.n) {
+      const int deg = a.degE[i];
+      double sumg[F], sumcg[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) sumg[f] = sumcg[f] = 0.0;
+      double C = 0.0;
+      // neighbours in chunks of 8: the list entries of a chunk are loaded
+      // together, then its rows are read from LDS
+      for (int k0 = 0; k0 < deg; k0 += 8) {
+        int jj[8];
+        double cc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          jj[u] = i;
+          cc[u] = 0.0;
+          if (k0 + u < deg) {
+            const size_t slot = (size_t)(k0 + u) * a.n + i;
+            jj[u] = a.colE[slot];
+            cc[u] = (m > 0) ? fmin(dprev * a.qE[slot], 1.0) : 1.0 - a.s[a.eidE[slot]];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (k0 + u < deg) {
+            C += cc[u];
+            const TG *rowj = slab + (size_t)jj[u] * F;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+              const double xv = (double)rowj[f];
+              sumg[f] += xv;
+              sumcg[f] = fma(cc[u], xv, sumcg[f]);
+            }
+          }
+        }
+      }
+      const double inv1d = 1.0 / (1.0 + (double)deg);
+      const double S = (double)deg - C;
+#pragma unroll
+      for (int c4 = 0; c4 < C4; ++c4) {
+        const int f0 = fbase + 4 * c4;
+        if (f0 < a.ld) {
+          const size_t row = (size_t)i * a.ld + f0;
+          double ap[4], up[4], x[4], gi[4];
+          bool mk[4] = {true, true, true, true};
+          VecIO<4>::load(Ap + row, ap);
+          VecIO<4>::load(U + row, up);
+          VecIO<4>::load(X + row, x);
+          if (a.M) VecIO<4>::load_mask(a.M + row, mk);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) gi[v] = (double)slab[(size_t)i * F + 4 * c4 + v];
+          double u[4], an[4], gn[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int f = 4 * c4 + v;
+            double uu;
+            if (m > 0) {
+              const double y = mk[v] ? x[v] : up[v];
+              uu = ap[v] + theta * (y - ap[v]);
+            } else {
+              uu = up[v];
+            }
+            uu = round_to<TS>(uu);
+            const double jac = sumcg[f] - C * gi[v];
+            const double h = S * gi[v] - (sumg[f] - sumcg[f]);
+            double anew = ap[v] + (uu - ap[v] + jac) * inv1d;
+            anew = round_to<TS>(anew);
+            const double gq = round_to<TG>(anew);
+            u[v] = uu; an[v] = anew; gn[v] = gq;
+            const double dua = uu - anew;
+            ps[0] = fma(dua, dua, ps[0]);
+            if (mk[v]) { const double r = x[v] - uu; ps[3] = fma(r, r, ps[3]); }
+            ps[4] = fma(uu, uu, ps[4]);
+            ps[5] = fma(h, gq, ps[5]);
+          }
+          VecIO<4>::store(U + row, u);
+          VecIO<4>::store(An + row, an);
+          if (Traits<PREC>::mirror) VecIO<4>::store(Gn + row, gn);
+          if (winU) {
+            double us[4];
+            VecIO<4>::load(Us + row, us);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) { const double du = u[v] - us[v]; ps[2] = fma(du, du, ps[2]); }
+          }
+          if (snapU0 || winU) VecIO<4>::store(Us + row, u);
+          if (initA) VecIO<4>::store(As + row, ap);
+          if (winA) {
+            double prev[4];
+            if (m == 0) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) prev[v] = ap[v];
+            } else {
+              VecIO<4>::load(As + row, prev);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) { const double da = an[v] - prev[v]; ps[1] = fma(da, da, ps[1]); }
+            VecIO<4>::store(As + row, an);
+          }
+        }
+      }
+    }
+  }
+  block_sum<kPointSums>(ps, scratch);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kPointSums; ++q) a.psum[(size_t)lb * 8 + q] = ps[q];
+  }
+}
+
 // --------------------------------------------------- per-edge bookkeeping
 // Per-edge inputs of the bookkeeping, loaded ahead of the row gathers.
 struct EdgeIn {
@@ -863,6 +1021,8 @@ __global__ __launch_bounds__(1024) void k_components(int n, int E, const int32_t
 // ====================================================================== host
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+constexpr int64_t kSlabBytes = 128 * 1024;  // LDS budget of the slab point sweep
+
 static size_t ts_size(int prec) { return prec == kF32 ? 4 : 8; }
 static size_t tx_size(int prec) { return prec == kF64 ? 8 : 4; }
 static size_t tg_size(int prec) { return prec == kF64 ? 8 : 4; }
@@ -941,8 +1101,42 @@ static int launch_edge_p(Problem *P, int init, int nbp) {
   return rblocks;
 }
 
+template <int PREC, int F>
+static void launch_point_slab_t(Problem *P, int blocks) {
+  PointArgs pa{(int)P->n, (int)P->ld, P->ntile, 0, 0,
+               P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
+               P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_rho, P->cur_K,
+               P->psum, P->sc};
+  const size_t lds = (size_t)P->n * F * sizeof(typename Traits<PREC>::TG);
+  hipLaunchKernelGGL((k_point_slab<PREC, F>), dim3(blocks), dim3(kBlock), lds, P->stream, pa);
+}
+
+template <int PREC>
+static void set_slab_attr() {
+  (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+}
+
+// Blocks of the point sweep (its partials count).
+static int point_blocks(Problem *P) {
+  if (P->slab_f > 0) return (int)(cdiv(P->ntile * cdiv(P->n, kBlock), kXcds) * kXcds);
+  return sweep_grid(P->n * P->ntile).blocks;
+}
+
 template <int PREC>
 static void launch_point_p(Problem *P, const Launch &Lp) {
+  if (P->slab_f > 0) {
+    const int blocks = point_blocks(P);
+    switch (P->slab_f) {
+      case 4: launch_point_slab_t<PREC, 4>(P, blocks); break;
+      case 8: launch_point_slab_t<PREC, 8>(P, blocks); break;
+      case 16: launch_point_slab_t<PREC, 16>(P, blocks); break;
+      default: launch_point_slab_t<PREC, 32>(P, blocks); break;
+    }
+    return;
+  }
   switch (P->vec) {
     case 1: launch_point_t<PREC, 1>(P, Lp); break;
     case 2: launch_point_t<PREC, 2>(P, Lp); break;
@@ -954,17 +1148,18 @@ static void launch_iteration(Problem *P) {
   hipEvent_t *ev = prof_slot(P);
   if (ev) (void)hipEventRecord(ev[0], P->stream);
   const Launch Lp = sweep_grid(P->n * P->ntile);
+  const int nbp = point_blocks(P);
   if (P->precision == kF32) launch_point_p<kF32>(P, Lp);
   else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
   else launch_point_p<kMixed>(P, Lp);
   if (ev) (void)hipEventRecord(ev[1], P->stream);
   int nbe;
-  if (P->precision == kF32) nbe = launch_edge_p<kF32>(P, 0, Lp.blocks);
-  else if (P->precision == kF64) nbe = launch_edge_p<kF64>(P, 0, Lp.blocks);
-  else nbe = launch_edge_p<kMixed>(P, 0, Lp.blocks);
+  if (P->precision == kF32) nbe = launch_edge_p<kF32>(P, 0, nbp);
+  else if (P->precision == kF64) nbe = launch_edge_p<kF64>(P, 0, nbp);
+  else nbe = launch_edge_p<kMixed>(P, 0, nbp);
   if (ev) (void)hipEventRecord(ev[2], P->stream);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, P->stream, (const double *)P->psum,
-                     Lp.blocks, (const double *)P->esum, nbe, P->trace, P->sc);
+                     nbp, (const double *)P->esum, nbe, P->trace, P->sc);
   if (ev) (void)hipEventRecord(ev[3], P->stream);
 }
 
@@ -1038,13 +1233,28 @@ static cc_status dmalloc(void **p, size_t bytes) {
   } while (0)
 
 static void choose_tiles(Problem *P) {
-  // tile width 64*vec features; wider tiles for wide data
+  // point sweep: the LDS slab variant when an n x F tile of the gather copy
+  // fits (F = 32, 16, 8 or 4 features), else a wave per (point, 64*vec tile)
+  const int64_t tg = (P->precision == kF64) ? 8 : 4;
+  int slab = 0;
+  const char *es = getenv("CCMI_SLAB_F");
+  if (es) slab = atoi(es);
+  if (slab != 0 && slab != 4 && slab != 8 && slab != 16 && slab != 32) slab = -1;
+  if (slab == -1 || !es) {
+    slab = 0;
+    for (int f : {16, 32, 8, 4}) {
+      if (P->n * f * tg <= kSlabBytes) { slab = f; break; }
+    }
+  }
+  if (slab > 0 && P->n * slab * tg > kSlabBytes) slab = 0;
+  P->slab_f = slab;
+  P->ell_cm = slab > 0;
   const char *env = getenv("CCMI_VEC");
   int vec = 0;
   if (env) vec = atoi(env);
-  if (vec != 1 && vec != 2 && vec != 4) vec = P->p > 2048 ? 4 : (P->p > 96 ? 2 : 1);
+  if (vec != 1 && vec != 2 && vec != 4) vec = P->p > 1024 ? 4 : (P->p > 96 ? 2 : 1);
   P->vec = vec;
-  P->tile_w = kWave * vec;
+  P->tile_w = slab > 0 ? slab : kWave * vec;
   P->ntile = (int)cdiv(P->ld, P->tile_w);
   // edge sweep: one tile over the whole row when it is at most 1024 wide
   if (P->ld <= 1024) {
@@ -1113,6 +1323,11 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   P->n = n; P->p = p; P->E = n_edges; P->ld = (p + 3) / 4 * 4;
   P->precision = precision; P->stream = stream; P->has_mask = mask != nullptr;
   choose_tiles(P);
+  if (P->slab_f > 0) {
+    if (precision == kF32) set_slab_attr<kF32>();
+    else if (precision == kF64) set_slab_attr<kF64>();
+    else set_slab_attr<kMixed>();
+  }
   struct Guard { Problem *&P; bool ok = false; ~Guard() { if (!ok) problem_free(P); } } guard{P};
 
   const size_t nl = (size_t)n * P->ld;
@@ -1143,7 +1358,8 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   CC_TRY(dmalloc((void **)&P->qe, E * 8));
   CC_TRY(dmalloc((void **)&P->epos, 2 * E * 4));
   CC_TRY(dmalloc((void **)&P->part, E * (P->efused ? 1 : P->entile) * 8));
-  CC_TRY(dmalloc((void **)&P->psum, kMaxBlocks * 8 * 8));
+  // one row of point partials per block of the point sweep
+  CC_TRY(dmalloc((void **)&P->psum, std::max<int64_t>(kMaxBlocks, point_blocks(P)) * 8 * 8));
   CC_TRY(dmalloc((void **)&P->esum, kMaxBlocks * 4 * 8));
   CC_TRY(dmalloc((void **)&P->sc, sizeof(DevScalars)));
   CC_TRY(dmalloc((void **)&P->ncl_dev, 4));
@@ -1182,10 +1398,13 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   const int64_t S = std::max<int64_t>(maxdeg, 1);
   P->ell_s = (int)S;
   std::vector<int32_t> hdegE(n), hcolE(n * S, 0), heidE(n * S, 0), hposE(2 * E);
+  // row-major (entry k of i at i*S + k) for the wave-per-point sweep,
+  // column-major (k*n + i) for the slab sweep
+  auto ell_slot = [&](int64_t i, int64_t k) -> int64_t { return P->ell_cm ? k * n + i : i * S + k; };
   for (int64_t i = 0; i < n; ++i) {
     hdegE[i] = rp[i + 1] - rp[i];
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-      const int64_t slot = i * S + (k - rp[i]);
+      const int64_t slot = ell_slot(i, k - rp[i]);
       hcolE[slot] = hcol[k];
       heidE[slot] = heid[k];
     }
@@ -1194,7 +1413,7 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
     // hpos holds CSR positions; map them to ELL slots
     const int32_t k = hpos[e2];
     const int64_t row = (e2 % 2 == 0) ? hi[e2 / 2] : hj[e2 / 2];
-    hposE[e2] = (int32_t)(row * S + (k - rp[row]));
+    hposE[e2] = (int32_t)ell_slot(row, k - rp[row]);
   }
   if ((int64_t)n * S > ((int64_t)1 << 31) - 1) { set_error("neighbour lists too large"); return CC_ERR_INVALID_ARG; }
   CC_TRY(dmalloc((void **)&P->degE, n * 4));

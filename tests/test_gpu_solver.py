@@ -219,3 +219,34 @@ def test_invalid_inputs_rejected(cc):
         _gpu(cc, X, None, np.vstack([E, E[:1]]), np.r_[w, w[:1]], "mixed")  # duplicate
     with pytest.raises(cc.CCError):
         _gpu(cc, X, None, E, -w, "mixed")
+
+
+# ------------------------------------------------------- kernel variants
+# The point sweep has a wave-per-(point, tile) form (CCMI_SLAB_F=0, tile
+# width 64*CCMI_VEC) and an LDS-slab form (CCMI_SLAB_F = feature-tile width);
+# wide rows (> 1024 features) switch the edge sweep to per-tile partials.
+# Each variant must reproduce the oracle's FP64 trajectory.
+@pytest.mark.parametrize("slab,vec", [("0", "1"), ("0", "2"), ("0", "4"),
+                                      ("4", "0"), ("8", "0"), ("16", "0"), ("32", "0")])
+def test_point_kernel_variants(cc, slab, vec, monkeypatch):
+    monkeypatch.setenv("CCMI_SLAB_F", slab)
+    monkeypatch.setenv("CCMI_VEC", vec)
+    X, M, E, w, _ = reduced_expression(n=300, p=150)  # ragged last tile for every width
+    st, _ = oracle_jacobi(X, M, E, w).solve(3.0, mm.Opts(tol=0, max_iter=80, proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, "f64") as g:
+        g.solve(3.0, tol=0.0, max_iter=80)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    assert rel_max(U, st.U) < 1e-11
+    assert rel_max(A, st.A) < 1e-11
+    assert np.abs(s - st.s).max() < 1e-9
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-11), ("mixed", 2e-6)])
+def test_wide_rows_edge_tiles(cc, precision, tol):
+    X, M, E, w, _ = reduced_expression(n=60, p=1100)  # 1100 > 1024: tiled edge sweep
+    st, _ = oracle_jacobi(X, M, E, w).solve(20.0, mm.Opts(tol=0, max_iter=60, proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, precision) as g:
+        g.solve(20.0, tol=0.0, max_iter=60)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    assert rel_max(U, st.U) < tol
+    assert rel_max(A, st.A) < tol
