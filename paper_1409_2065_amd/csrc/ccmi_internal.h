@@ -50,6 +50,9 @@ struct Problem {
   int entile = 1;     // edge-sweep tiles (1: the fused edge kernel)
   int npass = 4;      // 64-feature passes per edge tile
   bool efused = true;
+  bool eslab = false;        // wide rows, small n: LDS-slab edge sweep
+  int eslab_tpg = 1;         // feature tiles per block of the slab edge sweep
+  int eslab_ntf = 1;         // feature tiles of width slab_f
   // device buffers
   void *X = nullptr;         // n x ld, float (f32/mixed) or double (f64)
   uint8_t *M = nullptr;      // n x ld or null

@@ -836,6 +836,72 @@ __global__ __launch_bounds__(kBlock) void k_edge_tiles(EdgeArgs a) {
   }
 }
 
+// Wide rows with small n: one 1024-thread block per group of consecutive
+// F-feature tiles.  For each tile the block stages the new A (gather copy)
+// of all n points in LDS; each thread keeps FP64 accumulators of
+// (a_i - a_j)^2 for up to kEdgesPerThread edges across the group's tiles and
+// writes one partial per (edge, group) for k_edge_reduce.
+constexpr int kEdgesPerThread = 16;
+
+template <int PREC, int F>
+__global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_group, int ntiles_f) {
+  using TG = typename Traits<PREC>::TG;
+  constexpr int C4 = F / 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  TG *slab = reinterpret_cast<TG *>(smem);
+  DevScalars *sc = a.sc;
+  if (!a.init && sc->done) return;
+  const int pa = sc->pa;
+  const int buf = a.init ? pa : (pa ^ 1);
+  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
+  const int g = logical_block();
+  const int t0 = g * tiles_per_group, t1 = min(t0 + tiles_per_group, ntiles_f);
+  const int E = a.es.E;
+  int ei[kEdgesPerThread], ej[kEdgesPerThread];
+  double acc[kEdgesPerThread];
+#pragma unroll
+  for (int u = 0; u < kEdgesPerThread; ++u) {
+    const int e = threadIdx.x + u * blockDim.x;
+    ei[u] = 0; ej[u] = 0; acc[u] = 0.0;
+    if (e < E) { ei[u] = a.ei[e]; ej[u] = a.ej[e]; }
+  }
+  for (int t = t0; t < t1; ++t) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < a.n * C4; idx += blockDim.x) {
+      const int row = idx / C4, c = idx - row * C4;
+      const int f = t * F + 4 * c;
+      TG v[4] = {(TG)0, (TG)0, (TG)0, (TG)0};
+      if (f < a.ld) RawIO<TG, 4>::load(Gc + (size_t)row * a.ld + f, v);
+      TG *dst = slab + (size_t)row * F + 4 * c;
+      dst[0] = v[0]; dst[1] = v[1]; dst[2] = v[2]; dst[3] = v[3];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kEdgesPerThread; ++u) {
+      const int e = threadIdx.x + u * blockDim.x;
+      if (e < E) {
+        const TG *ri = slab + (size_t)ei[u] * F;
+        const TG *rj = slab + (size_t)ej[u] * F;
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          const double d = (double)ri[f] - (double)rj[f];
+          acc[u] = fma(d, d, acc[u]);
+        }
+      }
+    }
+  }
+  if (g * tiles_per_group >= ntiles_f) {
+    // a padding block (grid rounded up to the XCD count) owns no tiles
+#pragma unroll
+    for (int u = 0; u < kEdgesPerThread; ++u) acc[u] = 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kEdgesPerThread; ++u) {
+    const int e = threadIdx.x + u * blockDim.x;
+    if (e < E) a.part[(size_t)e * a.ntile + g] = acc[u];
+  }
+}
+
 // ------------------------------------------------------- k_edge_reduce
 // Wide rows: per edge, the tile partials in fixed order, then the same
 // per-edge bookkeeping and iteration finish as the fused edge kernel.
@@ -1092,9 +1158,21 @@ static int launch_edge_p(Problem *P, int init, int nbp) {
     }
     return Le.blocks;
   }
-  const Launch Le = sweep_grid(P->n * P->entile);
-  hipLaunchKernelGGL((k_edge_tiles<PREC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream,
-                     edge_args(P, Le, init, nbp));
+  if (P->eslab) {
+    const Launch Ls{P->entile, 0, 0};
+    const EdgeArgs ea = edge_args(P, Ls, init, nbp);
+    const size_t lds = (size_t)P->n * P->slab_f * sizeof(typename Traits<PREC>::TG);
+    switch (P->slab_f) {
+      case 4: hipLaunchKernelGGL((k_edge_slab<PREC, 4>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
+      case 8: hipLaunchKernelGGL((k_edge_slab<PREC, 8>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
+      case 16: hipLaunchKernelGGL((k_edge_slab<PREC, 16>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
+      default: hipLaunchKernelGGL((k_edge_slab<PREC, 32>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
+    }
+  } else {
+    const Launch Le = sweep_grid(P->n * P->entile);
+    hipLaunchKernelGGL((k_edge_tiles<PREC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream,
+                       edge_args(P, Le, init, nbp));
+  }
   const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
   ReduceArgs ra{P->entile, nbp, init, P->part, edge_state(P), P->esum, P->psum, P->trace, P->sc};
   hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
@@ -1113,6 +1191,10 @@ static void launch_point_slab_t(Problem *P, int blocks) {
 
 template <int PREC>
 static void set_slab_attr() {
+  (void)hipFuncSetAttribute((const void *)k_edge_slab<PREC, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_edge_slab<PREC, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_edge_slab<PREC, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_edge_slab<PREC, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
   (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
   (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
   (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
@@ -1267,6 +1349,16 @@ static void choose_tiles(Problem *P) {
     P->npass = 4;
     P->entile = (int)cdiv(P->ld, 256);
     P->efused = false;
+    // small n: stage tiles in LDS and keep per-edge accumulators in registers
+    const char *ee = getenv("CCMI_EDGE_SLAB");
+    const bool allow = !ee || atoi(ee) != 0;
+    if (allow && P->slab_f > 0 && P->E <= 1024 * 16) {
+      P->eslab = true;
+      P->eslab_ntf = (int)cdiv(P->ld, P->slab_f);
+      P->eslab_tpg = (int)cdiv(P->eslab_ntf, 256);
+      const int64_t groups = cdiv(P->eslab_ntf, P->eslab_tpg);
+      P->entile = (int)(cdiv(groups, kXcds) * kXcds);  // one partial column per block
+    }
   }
 }
 

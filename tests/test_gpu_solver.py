@@ -250,3 +250,17 @@ def test_wide_rows_edge_tiles(cc, precision, tol):
         U, A, s = (t.cpu().numpy() for t in g.get_state())
     assert rel_max(U, st.U) < tol
     assert rel_max(A, st.A) < tol
+
+
+@pytest.mark.parametrize("edge_slab", ["0", "1"])
+def test_wide_rows_edge_variants(cc, edge_slab, monkeypatch):
+    """Wide rows: the per-tile edge partials (CCMI_EDGE_SLAB=0) and the LDS
+    slab edge sweep agree with the oracle's trajectory."""
+    monkeypatch.setenv("CCMI_EDGE_SLAB", edge_slab)
+    X, M, E, w, _ = reduced_expression(n=60, p=1100)
+    st, _ = oracle_jacobi(X, M, E, w).solve(20.0, mm.Opts(tol=0, max_iter=40, proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, "f64") as g:
+        g.solve(20.0, tol=0.0, max_iter=40)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    assert rel_max(U, st.U) < 1e-11
+    assert np.abs(s - st.s).max() < 1e-9
