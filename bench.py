@@ -101,7 +101,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
-              "the multi-GPU sharding is a design note, not part of this build.", file=sys.stderr)
+              "feature sharding across GPUs is described in the design notes and not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

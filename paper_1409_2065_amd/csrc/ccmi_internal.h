@@ -52,7 +52,8 @@ struct Problem {
   bool efused = true;
   bool eslab = false;        // wide rows, small n: LDS-slab edge sweep
   int eslab_tpg = 1;         // feature tiles per block of the slab edge sweep
-  int eslab_ntf = 1;         // feature tiles of width slab_f
+  int eslab_ntf = 1;         // feature tiles of width edge_f
+  int edge_f = 0;            // LDS tile width of the slab edge sweep
   // device buffers
   void *X = nullptr;         // n x ld, float (f32/mixed) or double (f64)
   uint8_t *M = nullptr;      // n x ld or null

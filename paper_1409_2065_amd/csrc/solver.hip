@@ -1161,8 +1161,8 @@ static int launch_edge_p(Problem *P, int init, int nbp) {
   if (P->eslab) {
     const Launch Ls{P->entile, 0, 0};
     const EdgeArgs ea = edge_args(P, Ls, init, nbp);
-    const size_t lds = (size_t)P->n * P->slab_f * sizeof(typename Traits<PREC>::TG);
-    switch (P->slab_f) {
+    const size_t lds = (size_t)P->n * P->edge_f * sizeof(typename Traits<PREC>::TG);
+    switch (P->edge_f) {
       case 4: hipLaunchKernelGGL((k_edge_slab<PREC, 4>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
       case 8: hipLaunchKernelGGL((k_edge_slab<PREC, 8>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
       case 16: hipLaunchKernelGGL((k_edge_slab<PREC, 16>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
@@ -1317,24 +1317,26 @@ static cc_status dmalloc(void **p, size_t bytes) {
 static void choose_tiles(Problem *P) {
   // point sweep: the LDS slab variant when an n x F tile of the gather copy
   // fits (F = 32, 16, 8 or 4 features), else a wave per (point, 64*vec tile)
+  // The wave kernel is the default: the slab variant runs one wave per SIMD
+  // and measured slower on both the p = 500 and the p = 20000 workloads; it
+  // is kept as an option (CCMI_SLAB_F = 4, 8, 16 or 32).
   const int64_t tg = (P->precision == kF64) ? 8 : 4;
   int slab = 0;
   const char *es = getenv("CCMI_SLAB_F");
   if (es) slab = atoi(es);
-  if (slab != 0 && slab != 4 && slab != 8 && slab != 16 && slab != 32) slab = -1;
-  if (slab == -1 || !es) {
-    slab = 0;
-    for (int f : {16, 32, 8, 4}) {
-      if (P->n * f * tg <= kSlabBytes) { slab = f; break; }
-    }
-  }
+  if (slab != 4 && slab != 8 && slab != 16 && slab != 32) slab = 0;
   if (slab > 0 && P->n * slab * tg > kSlabBytes) slab = 0;
   P->slab_f = slab;
   P->ell_cm = slab > 0;
+  // edge sweep over wide rows: LDS tile width (independent of the above)
+  P->edge_f = 0;
+  for (int f : {16, 8, 4}) {
+    if (P->n * f * tg <= kSlabBytes / 2) { P->edge_f = f; break; }
+  }
   const char *env = getenv("CCMI_VEC");
   int vec = 0;
   if (env) vec = atoi(env);
-  if (vec != 1 && vec != 2 && vec != 4) vec = P->p > 1024 ? 4 : (P->p > 96 ? 2 : 1);
+  if (vec != 1 && vec != 2 && vec != 4) vec = P->p > 256 ? 4 : (P->p > 96 ? 2 : 1);
   P->vec = vec;
   P->tile_w = slab > 0 ? slab : kWave * vec;
   P->ntile = (int)cdiv(P->ld, P->tile_w);
@@ -1352,9 +1354,9 @@ static void choose_tiles(Problem *P) {
     // small n: stage tiles in LDS and keep per-edge accumulators in registers
     const char *ee = getenv("CCMI_EDGE_SLAB");
     const bool allow = !ee || atoi(ee) != 0;
-    if (allow && P->slab_f > 0 && P->E <= 1024 * 16) {
+    if (allow && P->edge_f > 0 && P->E <= 1024 * 16) {
       P->eslab = true;
-      P->eslab_ntf = (int)cdiv(P->ld, P->slab_f);
+      P->eslab_ntf = (int)cdiv(P->ld, P->edge_f);
       P->eslab_tpg = (int)cdiv(P->eslab_ntf, 256);
       const int64_t groups = cdiv(P->eslab_ntf, P->eslab_tpg);
       P->entile = (int)(cdiv(groups, kXcds) * kXcds);  // one partial column per block
@@ -1415,7 +1417,7 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   P->n = n; P->p = p; P->E = n_edges; P->ld = (p + 3) / 4 * 4;
   P->precision = precision; P->stream = stream; P->has_mask = mask != nullptr;
   choose_tiles(P);
-  if (P->slab_f > 0) {
+  if (P->slab_f > 0 || P->eslab) {
     if (precision == kF32) set_slab_attr<kF32>();
     else if (precision == kF64) set_slab_attr<kF64>();
     else set_slab_attr<kMixed>();
