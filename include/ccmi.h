@@ -207,12 +207,13 @@ cc_status cc_get_trace(cc_problem_t prob, double *F, int64_t cap,
 /* ---------------------------------------------------------------------
  * Kernel timing
  * ---------------------------------------------------------------------
- * cc_profile: sample_every > 0 brackets the three kernels of every
+ * cc_profile: sample_every > 0 brackets the two stages of every
  * sample_every-th MM iteration with HIP events on the problem's stream and
  * accumulates their durations; 0 turns sampling off.  Enabling clears the
- * statistics.  cc_kernel_stats (host outputs, 3 entries each, in the order
- * point sweep, edge sweep, edge reduction) returns the mean duration in
- * milliseconds and the number of sampled launches. */
+ * statistics.  cc_kernel_stats (host outputs, 2 entries each: the point
+ * sweep, which begins by finishing the previous iteration, then the edge
+ * stage) returns the mean duration in milliseconds and the number of
+ * sampled launches. */
 cc_status cc_profile(cc_problem_t prob, int32_t sample_every);
 cc_status cc_kernel_stats(cc_problem_t prob, double *avg_ms, int64_t *launches);
 

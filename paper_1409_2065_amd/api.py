@@ -148,10 +148,10 @@ class Problem:
         check(_lib.load().cc_profile(self._h, int(sample_every)))
 
     def kernel_stats(self):
-        ms = (C.c_double * 3)()
-        cnt = (C.c_int64 * 3)()
+        ms = (C.c_double * 2)()
+        cnt = (C.c_int64 * 2)()
         check(_lib.load().cc_kernel_stats(self._h, ms, cnt))
-        names = ("point_sweep", "edge_sweep", "edge_reduce")
+        names = ("point_sweep", "edge_stage")
         return {nm: {"avg_ms": ms[q], "launches": cnt[q]} for q, nm in enumerate(names)}
 
     # -- state --

@@ -224,7 +224,7 @@ cc_status cc_kernel_stats(cc_problem_t prob, double *avg_ms, int64_t *launches) 
   Problem *P = reinterpret_cast<Problem *>(prob);
   if (hipStreamSynchronize(P->stream) != hipSuccess) { set_error("stream sync failed"); return CC_ERR_HIP; }
   harvest_profile(P);
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < 2; ++q) {
     avg_ms[q] = P->prof_n[q] ? P->prof_ms[q] / (double)P->prof_n[q] : 0.0;
     if (launches) launches[q] = P->prof_n[q];
   }

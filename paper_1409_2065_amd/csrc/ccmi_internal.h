@@ -18,14 +18,21 @@ constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
 constexpr int kMaxBlocks = 2048; // grid cap for the grid-stride sweeps
 constexpr int kPointSums = 6;    // per-block FP64 partial sums of the point pass
 constexpr int kEdgeSums = 3;     // per-block FP64 partial sums of the edge pass
+constexpr int kIterSums = kPointSums + kEdgeSums;
+constexpr int kEdgeBlock = 1024; // threads per block of the edge-stage kernels
+constexpr int kEdgeWaves = kEdgeBlock / kWave;
+constexpr int kEsumRows = 512;   // partial rows the edge stage leaves (column-major)
 
-// Device-resident iteration scalars.  Written by the host only through the
-// set-parameters kernel; read by every kernel of an iteration; advanced by
-// the last block of the edge-reduction kernel.
+// Device-resident iteration scalars, in two slots.  Written by the host
+// only through the set-parameters and reset kernels.  A point sweep reads
+// one slot, finishes the previous MM iteration (when one is pending) and its
+// block 0 writes the advanced scalars to the other slot, which the edge stage
+// and the next point sweep read.
 struct DevScalars {
   // per-solve constants
   double mu, rho, eps, thr;  // thr = tol * eta (0 disables the stop test)
-  int max_iter, record, K, mode_pad1;  // K = stop-test window
+  int max_iter, record, K;   // K = stop-test window
+  int pending;    // a sweep ran with these scalars and is not yet finished
   // iteration state
   int m;          // MM iteration index within the current solve
   int pa;         // buffer index holding A_{m-1} (and its edge norms)
@@ -34,8 +41,7 @@ struct DevScalars {
   double dA_prev; // ||A_{m-1} - A_{m-1-K}||^2 of the last A window
   double F_cur;   // F_{m-1} once iteration m-1 has finished
   double F_last, d_last, rel_last;
-  unsigned int counter; // last-block-done counter of the reduction kernel
-  unsigned int pad2;
+  unsigned int pad0, pad1;
 };
 
 enum Prec { kF32 = CC_PREC_F32, kMixed = CC_PREC_MIXED, kF64 = CC_PREC_F64 };
@@ -76,11 +82,14 @@ struct Problem {
   double cur_rho = 1.0;     // constants of the solve in progress
   int cur_K = 64;
   double *part = nullptr;    // E x entile edge partials
-  double *psum = nullptr;    // kMaxBlocks x 8 point partials
-  double *esum = nullptr;    // kMaxBlocks x 4 edge partials
+  double *psum = nullptr;    // point-sweep blocks x 8 point partials
+  double *esum = nullptr;    // kIterSums x kEsumRows, column-major: partial
+                             // rows of the edge stage (point sums gathered in)
+  int nbe = 1;               // partial rows the edge stage writes
   double *trace = nullptr;   // objective per iteration (record mode)
   int64_t trace_cap = 0, trace_count = 0;
-  DevScalars *sc = nullptr;
+  DevScalars *sc = nullptr;  // two slots
+  int slot = 0;              // slot holding the current scalars
   DevScalars *sc_host = nullptr; // pinned mirror
   int32_t *flag_host = nullptr;  // pinned
   int32_t *ncl_dev = nullptr;

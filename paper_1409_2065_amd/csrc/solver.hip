@@ -2,10 +2,14 @@
 //
 // One MM iteration m (Section "The Proximal Distance Algorithm", the block-
 // descent projection for sparse weights, and Section "Missing Data") runs as
-// three kernels over device-resident state:
+// two kernels over device-resident state:
 //
-//   k_point   for every point i and feature tile: finish the U update of
-//             iteration m-1, u_i = a'_i + theta (y_i - a'_i) with
+//   k_point   every block first finishes iteration m-1 from the partial rows
+//             the edge stage left: the same fixed-order sums in every block
+//             give d, the objective, the stopping test and the advanced
+//             scalars (block 0 stores them).  Then for every point i and
+//             feature tile: the U update
+//             u_i = a'_i + theta (y_i - a'_i) with
 //             theta = d/(d+rho) and y = x on observed entries, u elsewhere
 //             (the same as (d y + rho a)/(d + rho)); then one Jacobi sweep of
 //             the paper's block update
@@ -16,18 +20,19 @@
 //             (group soft-threshold) are recomputed on the fly from the edge
 //             norms and d of iteration m-1.  Per-block FP64 partial sums feed
 //             d, the objective and the stopping test.
-//   k_edge    per edge and tile: partial ||a_i - a_j||^2 of the new A.
-//   k_edge_reduce  per edge: ||b_e||, the terms of ||V - D A||^2 and of the
-//             penalty; the last block to finish reduces every partial in a
-//             fixed order and advances the iteration (d, objective, stop test).
+//   k_edge_fused (rows up to 1024 wide) or k_edge_slab / k_edge_tiles and
+//             k_edge_reduce (wider rows): per edge ||b_e|| of the new A, the
+//             terms of ||V - D A||^2 and of the penalty, and the q factors of
+//             the next sweep; each block also gathers a fixed subset of the
+//             point sweep's block partials into its partial row.
 //
 // ||V - D A||^2 is assembled as sum_e s_e^2 ||b'_e||^2
 //   - 2 sum_i <h_i, a_i> + sum_e ||b_e||^2, with h_i = sum_j s_ij (a'_i - a'_j)
 // accumulated by k_point in FP64, so the edge pass gathers one row per edge.
 //
 // Pair arithmetic is FP64 on values read from the gather copy of A (FP32 in
-// the F32 and MIXED precisions); every reduction is FP64 and atomic-free
-// except the single last-block counter.  Blocks are mapped to feature tiles
+// the F32 and MIXED precisions); every reduction is FP64, atomic-free and in
+// a fixed order, so runs are bitwise repeatable.  Blocks are mapped to feature tiles
 // tile-major per XCD so that each XCD's L2 holds the rows of the tiles it
 // sweeps.
 
@@ -113,6 +118,18 @@ template <> struct VecIO<1> {
   __device__ static void load_mask(const uint8_t *p, bool (&o)[1]) { o[0] = *p != 0; }
 };
 
+// Raw mask bytes of VEC consecutive entries (byte v in bits 8v..8v+7).
+template <int VEC> struct RawMask;
+template <> struct RawMask<4> {
+  __device__ static uint32_t load(const uint8_t *p) { return *reinterpret_cast<const uint32_t *>(p); }
+};
+template <> struct RawMask<2> {
+  __device__ static uint32_t load(const uint8_t *p) { return *reinterpret_cast<const uint16_t *>(p); }
+};
+template <> struct RawMask<1> {
+  __device__ static uint32_t load(const uint8_t *p) { return *p; }
+};
+
 // Raw vector loads (no conversion) for the software-pipelined gathers.
 template <typename T, int VEC> struct RawIO;
 template <> struct RawIO<float, 4> {
@@ -185,6 +202,29 @@ __device__ inline void block_sum(double (&v)[NV], double *scratch) {
   __syncthreads();
 }
 
+// Fixed-order block reduction whose result every thread receives (the xor
+// butterfly leaves the same value in every lane; the NW waves are then
+// summed in order).  scratch: NW * NV doubles, not reused by the caller
+// before its next barrier.
+template <int NV, int NW>
+__device__ inline void block_sum_all(double (&v)[NV], double *scratch) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) scratch[wave * NV + q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double acc = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) acc += scratch[w * NV + q];
+    v[q] = acc;
+  }
+}
+
 // Logical block index: physical block b runs on XCD b % 8 (round-robin
 // dispatch); XCD x is given the x-th contiguous eighth of the logical range,
 // so each XCD sweeps a contiguous run of feature tiles.
@@ -207,8 +247,12 @@ struct PointArgs {
   const double *s;      // state shrink factors (first iteration of a solve)
   double rho;           // constants of the solve
   int K;
-  double *psum;
-  DevScalars *sc;
+  double *psum;         // this sweep's block partials
+  const double *esum;   // partial rows of the previous edge stage
+  int nrows;            // how many
+  double *trace;
+  const DevScalars *sin;  // scalars of the previous iteration
+  DevScalars *sout;       // advanced scalars (block 0 writes)
 };
 
 // Per-edge bookkeeping shared by the fused edge kernel and the reduction
@@ -230,10 +274,9 @@ struct EdgeArgs {
   const int32_t *rowptr, *uptr, *col, *eid;  // CSR (wide-row tiles)
   double *part;         // E x ntile partial ||b||^2 (ntile > 1)
   EdgeState es;
-  double *esum;
-  const double *psum;
-  double *trace;
-  DevScalars *sc;
+  double *esum;         // partial rows (fused kernel)
+  const double *psum;   // point-sweep block partials, nbp rows
+  const DevScalars *sc; // scalars of the iteration in progress
 };
 
 struct ReduceArgs {
@@ -242,9 +285,75 @@ struct ReduceArgs {
   EdgeState es;
   double *esum;
   const double *psum;
-  double *trace;
-  DevScalars *sc;
+  const DevScalars *sc;
 };
+
+// ------------------------------------------------------- iteration finish
+// End of MM iteration h.m from the full sums v (point sums, then edge sums):
+// d, the objective, the windowed stop test and the advance of the scalars.
+__device__ inline void finish_scalars(DevScalars &h, const double (&v)[kIterSums], double *trace,
+                                      bool writer) {
+  const double uA2 = v[0], dAw = v[1], dUw = v[2], loss2 = v[3], u2 = v[4], cross = v[5];
+  const double Cs = v[6], As = v[7], pen = v[8];
+  const double viol = fmax(As - 2.0 * cross + Cs, 0.0);
+  const double d = sqrt(uA2 + viol + h.eps);
+  const double F = 0.5 * loss2 + h.mu * pen + h.rho * d;
+  const int m = h.m;
+  if (writer && h.record && trace) trace[m] = F;
+  if (!isfinite(d) || !isfinite(F)) {
+    h.status = CC_ERR_NUMERIC; h.done = 1; h.iters = m;
+    return;
+  }
+  const int K = h.K;
+  if (m >= 1) {
+    // iteration m-1 of the MM loop has now finished
+    h.F_last = h.F_cur;
+    h.d_last = h.d_prev;
+    if (m % K == 0) {
+      const double r = sqrt(dUw + h.dA_prev) / (double)K;
+      const double unorm = fmax(1.0, sqrt(u2));
+      h.rel_last = r / unorm;
+      if (h.thr > 0.0 && m - 1 >= 2 && r <= h.thr * unorm) {
+        h.done = 1; h.converged = 1; h.iters = m;
+        return;
+      }
+    }
+    if (m >= h.max_iter) {
+      h.done = 1; h.converged = 0; h.iters = m;
+      return;
+    }
+  }
+  h.F_cur = F;
+  h.d_prev = d;
+  if (m % K == K - 1) h.dA_prev = dAw;
+  h.pa ^= 1;
+  h.m = m + 1;
+}
+
+// Start of a point sweep: when a sweep is pending, sum the edge stage's
+// partial rows (column-major, the same order in every block) and finish its
+// iteration; block 0 stores the scalars of the iteration about to run (or
+// the final ones) in the other slot.  Blocks of kBlock threads; red:
+// kWavesPerBlock * kIterSums.
+__device__ inline DevScalars begin_iteration(const PointArgs &a, double *red) {
+  double v[kIterSums];
+#pragma unroll
+  for (int q = 0; q < kIterSums; ++q) v[q] = 0.0;
+  // issued before the scalars are known; unused when nothing is pending
+  for (int b = threadIdx.x; b < a.nrows; b += kBlock) {
+#pragma unroll
+    for (int q = 0; q < kIterSums; ++q) v[q] += a.esum[(size_t)q * kEsumRows + b];
+  }
+  DevScalars h = *a.sin;
+  const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+  if (h.pending && !h.done) {  // uniform
+    block_sum_all<kIterSums, kWavesPerBlock>(v, red);
+    finish_scalars(h, v, a.trace, writer);
+  }
+  h.pending = h.done ? 0 : 1;
+  if (writer) *a.sout = h;
+  return h;
+}
 
 // ------------------------------------------------------------- k_point
 template <int PREC, int VEC>
@@ -253,10 +362,41 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
   using TG = typename Traits<PREC>::TG;
   using TX = typename Traits<PREC>::TX;
   __shared__ double scratch[kWavesPerBlock * kPointSums];
-  DevScalars *sc = a.sc;
-  if (sc->done) return;
-  const int m = sc->m, pa = sc->pa;
-  const double rho = a.rho, dprev = sc->d_prev;
+  __shared__ double red[kWavesPerBlock * kIterSums];
+  const TX *X = reinterpret_cast<const TX *>(a.X);
+  TS *U = reinterpret_cast<TS *>(a.U);
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lb = logical_block();
+  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
+  const int W = kWave * VEC;
+
+  // The first item's loads that do not depend on the scalars (mask, the
+  // neighbour slots and their q, the U and X rows) are issued before the
+  // previous iteration is finished, so they overlap that reduction.
+  const int first = it0 + wave;
+  uint32_t mr0 = 0xffffffffu;
+  int jl0 = -1;
+  double ql0 = 0.0;
+  TS up0[VEC];
+  TX x0[VEC];
+  if (first < it1) {
+    const int t = first / a.n, i = first - t * a.n;
+    const int f0 = t * W + lane * VEC;
+    const size_t rowc = (size_t)i * a.ld + (f0 < a.ld ? f0 : 0);
+    if (a.M) mr0 = RawMask<VEC>::load(a.M + rowc);
+    if (lane < a.ell_s) {
+      jl0 = a.colE[i * a.ell_s + lane];
+      ql0 = a.qE[i * a.ell_s + lane];  // unused in the first iteration of a solve
+    }
+    RawIO<TS, VEC>::load(U + rowc, up0);
+    RawIO<TX, VEC>::load(X + rowc, x0);
+  }
+
+  const DevScalars hs = begin_iteration(a, red);
+  if (hs.done) return;
+  const int m = hs.m, pa = hs.pa;
+  const double rho = a.rho, dprev = hs.d_prev;
   const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
   // stop-test window: U snapshots at m = 0, K, 2K, ...; A snapshots at
   // m = K-1, 2K-1, ... (the start-of-solve A' seeds the first A window)
@@ -269,99 +409,128 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
   TS *An = reinterpret_cast<TS *>(pa == 0 ? a.A1 : a.A0);
   const TG *Gp = reinterpret_cast<const TG *>(pa == 0 ? a.G0 : a.G1);
   TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
-  const TX *X = reinterpret_cast<const TX *>(a.X);
-  TS *U = reinterpret_cast<TS *>(a.U);
-
-  const int lane = threadIdx.x % kWave;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lb = logical_block();
-  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
-  const int W = kWave * VEC;
   double ps[kPointSums] = {0, 0, 0, 0, 0, 0};
 
-  for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
+  for (int item = first; item < it1; item += kWavesPerBlock) {
     const int t = item / a.n, i = item - t * a.n;
     const int f0 = t * W + lane * VEC;
     const bool active = f0 < a.ld;
+    // Lanes past the row end load (and ignore) feature 0 of the same rows:
+    // the loads are unconditional, so the compiler's wait counts stay exact.
+    const int f0c = active ? f0 : 0;
     const size_t row = (size_t)i * a.ld + f0;
+    const size_t rowc = (size_t)i * a.ld + f0c;
     const int rs = i * a.ell_s;
-    const int deg = a.degE[i];
-    const int re = rs + deg;
-
-    double gi[VEC], ap[VEC], up[VEC], x[VEC];
-    bool mk[VEC];
+    // Mask (if any), neighbour slots (unused slots hold -1 and follow the
+    // used ones), then the point's own rows kept raw until the epilogue: the
+    // gathers wait only on the slot loads.
+    uint32_t mr = mr0;
+    int jl = jl0;
+    double ql = ql0;
+    TS upr[VEC];
+    TX xr[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) { upr[v] = up0[v]; xr[v] = x0[v]; }
+    if (item != first) {
+      if (a.M) mr = RawMask<VEC>::load(a.M + rowc);
+      jl = -1;
+      ql = 0.0;
+      if (lane < a.ell_s) {
+        jl = a.colE[rs + lane];
+        if (m > 0) ql = a.qE[rs + lane];
+      }
+      RawIO<TS, VEC>::load(U + rowc, upr);
+      RawIO<TX, VEC>::load(X + rowc, xr);
+    }
+    TG gr[VEC];
+    TS apr[VEC];
+    RawIO<TG, VEC>::load(Gp + rowc, gr);
+    RawIO<TS, VEC>::load(Ap + rowc, apr);
     double sumg[VEC], sumcg[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) { gi[v] = ap[v] = up[v] = x[v] = 0.0; mk[v] = true; sumg[v] = sumcg[v] = 0.0; }
-    if (active) {
-      VecIO<VEC>::load(Gp + row, gi);
-      VecIO<VEC>::load(Ap + row, ap);
-      VecIO<VEC>::load(U + row, up);
-      VecIO<VEC>::load(X + row, x);
-      if (a.M) VecIO<VEC>::load_mask(a.M + row, mk);
-    }
+    for (int v = 0; v < VEC; ++v) sumg[v] = sumcg[v] = 0.0;
     double C = 0.0;
-    for (int base = rs; base < re; base += kWave) {
-      const int cnt = min(kWave, re - base);
-      int jl = 0;
+    // One chunk of up to 64 neighbour slots (jl, ql per lane): count the
+    // used slots, form c, gather and accumulate; returns the count.
+    auto chunk = [&](int base, int jl, double ql) -> int {
+      const int cnt = __popcll(__ballot(jl >= 0));
       double cl = 0.0;
       if (lane < cnt) {
-        jl = a.colE[base + lane];
         // c = 1 - s with s the V-update shrink factor; from the state at the
         // first iteration of a solve, else min(d q, 1) = min(tau/||b||, 1)
-        cl = (m > 0) ? fmin(dprev * a.qE[base + lane], 1.0) : 1.0 - a.s[a.eidE[base + lane]];
+        cl = (m > 0) ? fmin(dprev * ql, 1.0) : 1.0 - a.s[a.eidE[base + lane]];
       }
-      // Gathers in batches of 8 rows, two batches in flight: batch k+8 is
-      // issued before batch k is accumulated.
-      auto issue = [&](int k0, TG (&r)[8][VEC], double (&c)[8]) {
+      // Gathers in batches of 8 rows, two batches in flight: batch b+1 is
+      // issued before batch b is accumulated.  Slots past cnt in the last
+      // batch read the point's own row with weight 0 and c = 0 (fma(1, x, s)
+      // rounds as s + x, so used slots sum exactly as plain additions).
+      auto issue = [&](int k0, TG (&r)[8][VEC], double (&c)[8], double (&wt)[8]) {
         int j[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) { j[q] = __builtin_amdgcn_readlane(jl, k0 + q); c[q] = readlane_d(cl, k0 + q); }
-        if (active) {
-#pragma unroll
-          for (int q = 0; q < 8; ++q) RawIO<TG, VEC>::load(Gp + (size_t)j[q] * a.ld + f0, r[q]);
+        for (int q = 0; q < 8; ++q) {
+          const bool ok = k0 + q < cnt;
+          j[q] = ok ? __builtin_amdgcn_readlane(jl, k0 + q) : i;
+          c[q] = ok ? readlane_d(cl, k0 + q) : 0.0;
+          wt[q] = ok ? 1.0 : 0.0;
         }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) RawIO<TG, VEC>::load(Gp + (size_t)j[q] * a.ld + f0c, r[q]);
       };
-      auto consume = [&](const TG (&r)[8][VEC], const double (&c)[8]) {
+      auto consume = [&](const TG (&r)[8][VEC], const double (&c)[8], const double (&wt)[8]) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) C += c[q];
-        if (active) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 8; ++q) {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-              const double xv = (double)r[q][v];
-              sumg[v] += xv;
-              sumcg[v] = fma(c[q], xv, sumcg[v]);
-            }
+          for (int v = 0; v < VEC; ++v) {
+            const double xv = (double)r[q][v];
+            sumg[v] = fma(wt[q], xv, sumg[v]);
+            sumcg[v] = fma(c[q], xv, sumcg[v]);
           }
         }
       };
-      const int nfull = cnt & ~7;
+      // Every issue is unconditional (a batch past the end is all weight 0),
+      // so the wait before each accumulation counts only the batch it needs.
+      const int nbat = (cnt + 7) >> 3;
       TG ra[8][VEC], rb[8][VEC];
-      double ca[8], cb[8];
-      if (nfull > 0) issue(0, ra, ca);
-      for (int k0 = 0; k0 < nfull; k0 += 16) {
-        if (k0 + 8 < nfull) issue(k0 + 8, rb, cb);
-        consume(ra, ca);
-        if (k0 + 8 >= nfull) break;
-        if (k0 + 16 < nfull) issue(k0 + 16, ra, ca);
-        consume(rb, cb);
-      }
-      int k = nfull;
-      for (; k < cnt; ++k) {
-        const int j0 = __builtin_amdgcn_readlane(jl, k);
-        const double c0 = readlane_d(cl, k);
-        C += c0;
-        if (active) {
-          double x0[VEC];
-          VecIO<VEC>::load(Gp + (size_t)j0 * a.ld + f0, x0);
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) { sumg[v] += x0[v]; sumcg[v] = fma(c0, x0[v], sumcg[v]); }
+      double ca[8], cb[8], wa[8], wb[8];
+      if (nbat > 0) {
+        issue(0, ra, ca, wa);
+        for (int b = 0;; b += 2) {
+          issue(8 * (b + 1), rb, cb, wb);
+          consume(ra, ca, wa);
+          if (b + 1 >= nbat) break;
+          issue(8 * (b + 2), ra, ca, wa);
+          consume(rb, cb, wb);
+          if (b + 2 >= nbat) break;
         }
+      }
+      return cnt;
+    };
+    // the first chunk is straight-line code after the loads above, so its
+    // gathers wait only on the slot loads
+    int deg = chunk(rs, jl, ql);
+    if (deg == kWave) {
+      for (int k64 = kWave; k64 < a.ell_s; k64 += kWave) {
+        int jk = -1;
+        double qk = 0.0;
+        if (lane < a.ell_s - k64) {
+          jk = a.colE[rs + k64 + lane];
+          if (m > 0) qk = a.qE[rs + k64 + lane];
+        }
+        const int cnt = chunk(rs + k64, jk, qk);
+        deg += cnt;
+        if (cnt < kWave) break;
       }
     }
     if (active) {
+      double gi[VEC], ap[VEC], up[VEC], x[VEC];
+      bool mk[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        gi[v] = (double)gr[v]; ap[v] = (double)apr[v]; up[v] = (double)upr[v]; x[v] = (double)xr[v];
+        mk[v] = ((mr >> (8 * v)) & 0xffu) != 0u;
+      }
       const double inv1d = 1.0 / (1.0 + (double)deg);
       const double S = (double)deg - C;
       double u[VEC], an[VEC], gn[VEC];
@@ -435,10 +604,11 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   TG *slab = reinterpret_cast<TG *>(smem);
   __shared__ double scratch[kWavesPerBlock * kPointSums];
-  DevScalars *sc = a.sc;
-  if (sc->done) return;
-  const int m = sc->m, pa = sc->pa;
-  const double rho = a.rho, dprev = sc->d_prev;
+  __shared__ double red[kWavesPerBlock * kIterSums];
+  const DevScalars hs = begin_iteration(a, red);
+  if (hs.done) return;
+  const int m = hs.m, pa = hs.pa;
+  const double rho = a.rho, dprev = hs.d_prev;
   const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
   const int K = a.K;
   const bool snapU0 = (m == 0), winU = (m > 0) && (m % K == 0);
@@ -578,15 +748,15 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
 }
 
 // --------------------------------------------------- per-edge bookkeeping
-// Per-edge inputs of the bookkeeping, loaded ahead of the row gathers.
+// Per-edge inputs of the bookkeeping.  Both norm buffers are loaded and
+// the one of A' is picked where it is used, so nothing waits on the loads
+// before the row gathers are issued.
 struct EdgeIn {
-  double qprev, nbprev, w, s;
+  double qprev, n0, n1, w, s;
 };
 
-__device__ inline EdgeIn edge_prefetch(const EdgeState &es, int e, int pa) {
-  // both norm buffers are read so that the loads do not wait on pa
-  const double n0 = es.nb0[e], n1 = es.nb1[e];
-  return EdgeIn{es.qe[e], pa == 0 ? n0 : n1, es.w[e], es.s[e]};
+__device__ inline EdgeIn edge_prefetch(const EdgeState &es, int e) {
+  return EdgeIn{es.qe[e], es.nb0[e], es.nb1[e], es.w[e], es.s[e]};
 }
 
 // Given ||b_e||^2 of the new A_m: store ||b_e||; in an iteration also take
@@ -602,7 +772,7 @@ __device__ inline void edge_update(const EdgeState &es, int e, double nb2, const
   const int m = sc->m;
   const double sv = (m > 0) ? 1.0 - fmin(sc->d_prev * in.qprev, 1.0) : in.s;
   es.s[e] = sv;
-  const double np = in.nbprev;
+  const double np = pa == 0 ? in.n0 : in.n1;
   t3[0] += nb2;
   t3[1] += (sv * np) * (sv * np);
   t3[2] += in.w * sv * np;
@@ -612,100 +782,25 @@ __device__ inline void edge_update(const EdgeState &es, int e, double nb2, const
   es.qE[es.epos[2 * e + 1]] = q;
 }
 
-// ------------------------------------------------------- iteration finish
-// Fixed-order sums of every point and edge partial, then d, the objective,
-// the windowed stop test and the advance of the iteration scalars.  All
-// loads (scalars and partials) are issued before anything waits on them.
-__device__ void finish_iteration(const double *psum, int nbp, const double *esum, int nbe,
-                                 double *trace, DevScalars *sc, double *red) {
-  const DevScalars h = *sc;  // snapshot of the iteration scalars
-  double v[kPointSums + kEdgeSums];
-#pragma unroll
-  for (int q = 0; q < kPointSums + kEdgeSums; ++q) v[q] = 0.0;
-  for (int b0 = threadIdx.x; b0 < nbp; b0 += 4 * blockDim.x) {
-    double r[4][kPointSums];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int b = b0 + u * blockDim.x;
-#pragma unroll
-      for (int q = 0; q < kPointSums; ++q) r[u][q] = (b < nbp) ? psum[(size_t)b * 8 + q] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-      for (int q = 0; q < kPointSums; ++q) v[q] += r[u][q];
-    }
+// Partial row of an edge-stage block: the point-sweep partials of rows
+// blockIdx.x, blockIdx.x + gridDim.x, ... (pt, held by threads 0..5) and the
+// block's edge sums, stored column-major for the next point sweep.
+__device__ inline double gather_point_partials(const double *psum, int nbp) {
+  double pt = 0.0;
+  if (threadIdx.x < kPointSums) {
+    for (int r = blockIdx.x; r < nbp; r += gridDim.x) pt += psum[(size_t)r * 8 + threadIdx.x];
   }
-  for (int b0 = threadIdx.x; b0 < nbe; b0 += 4 * blockDim.x) {
-    double r[4][kEdgeSums];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int b = b0 + u * blockDim.x;
-#pragma unroll
-      for (int q = 0; q < kEdgeSums; ++q) r[u][q] = (b < nbe) ? esum[(size_t)b * 4 + q] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-      for (int q = 0; q < kEdgeSums; ++q) v[kPointSums + q] += r[u][q];
-    }
-  }
-  if (h.done) return;  // uniform
-  block_sum<kPointSums + kEdgeSums>(v, red);
-  if (threadIdx.x != 0) return;
-  const double uA2 = v[0], dAw = v[1], dUw = v[2], loss2 = v[3], u2 = v[4], cross = v[5];
-  const double Cs = v[6], As = v[7], pen = v[8];
-  const double viol = fmax(As - 2.0 * cross + Cs, 0.0);
-  const double d = sqrt(uA2 + viol + h.eps);
-  const double F = 0.5 * loss2 + h.mu * pen + h.rho * d;
-  const int m = h.m;
-  if (h.record && trace) trace[m] = F;
-  if (!isfinite(d) || !isfinite(F)) {
-    sc->status = CC_ERR_NUMERIC; sc->done = 1; sc->iters = m;
-    return;
-  }
-  const int K = h.K;
-  if (m >= 1) {
-    // iteration m-1 of the MM loop has now finished
-    sc->F_last = h.F_cur;
-    sc->d_last = h.d_prev;
-    if (m % K == 0) {
-      const double r = sqrt(dUw + h.dA_prev) / (double)K;
-      const double unorm = fmax(1.0, sqrt(u2));
-      sc->rel_last = r / unorm;
-      if (h.thr > 0.0 && m - 1 >= 2 && r <= h.thr * unorm) {
-        sc->done = 1; sc->converged = 1; sc->iters = m;
-        return;
-      }
-    }
-    if (m >= h.max_iter) {
-      sc->done = 1; sc->converged = 0; sc->iters = m;
-      return;
-    }
-  }
-  sc->F_cur = F;
-  sc->d_prev = d;
-  if (m % K == K - 1) sc->dA_prev = dAw;
-  sc->pa = h.pa ^ 1;
-  sc->m = m + 1;
+  return pt;
 }
 
-// Block partials of the edge terms (reduced in fixed order by k_finish).
-__device__ inline void edge_block_partials(double (&t3)[kEdgeSums], double *esum) {
-  __shared__ double red[kWavesPerBlock * kEdgeSums];
+__device__ inline void edge_block_partials(double (&t3)[kEdgeSums], double pt, double *esum) {
+  __shared__ double red[kEdgeWaves * kEdgeSums];
   block_sum<kEdgeSums>(t3, red);
+  if (threadIdx.x < kPointSums) esum[(size_t)threadIdx.x * kEsumRows + blockIdx.x] = pt;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < kEdgeSums; ++q) esum[(size_t)blockIdx.x * 4 + q] = t3[q];
+    for (int q = 0; q < kEdgeSums; ++q) esum[(size_t)(kPointSums + q) * kEsumRows + blockIdx.x] = t3[q];
   }
-}
-
-// One block: the end of an MM iteration.  Kernel boundaries order it after
-// every partial it reads, so no device-wide fences are needed.
-__global__ __launch_bounds__(1024) void k_finish(const double *psum, int nbp, const double *esum,
-                                                 int nbe, double *trace, DevScalars *sc) {
-  __shared__ double red[16 * (kPointSums + kEdgeSums)];
-  finish_iteration(psum, nbp, esum, nbe, trace, sc, red);
 }
 
 // -------------------------------------------------------------- k_edge
@@ -714,53 +809,69 @@ __global__ __launch_bounds__(1024) void k_finish(const double *psum, int nbp, co
 // over the row, 4 features per lane per 64-feature pass, reduces over its 16
 // lanes, and the quarter leader finishes the edge.
 template <int PREC, int NPASS>
-__global__ __launch_bounds__(kBlock) void k_edge_fused(EdgeArgs a) {
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
   using TG = typename Traits<PREC>::TG;
-  DevScalars *sc = a.sc;
+  const DevScalars *sc = a.sc;
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int q = lane / 16, l16 = lane % 16;
   const int lb = logical_block();
   const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
+  // An invalid quarter (past the last edge) works on the last edge and
+  // stores nothing; item < nitems guarantees E >= 1.  The first item's edge
+  // ends are loaded before the scalars, so both arrive together.
+  const int first = it0 + wave;
+  int i0 = 0, j0 = 0;
+  if (first < it1) {
+    const int e = 4 * first + q;
+    const int ec = e < a.es.E ? e : a.es.E - 1;
+    i0 = a.ei[ec];
+    j0 = a.ej[ec];
+  }
   if (!a.init && sc->done) return;
+  const double pt = a.init ? 0.0 : gather_point_partials(a.psum, a.nbp);
   const int pa = sc->pa;
   // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
   const int buf = a.init ? pa : (pa ^ 1);
   const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
   double t3[kEdgeSums] = {0.0, 0.0, 0.0};
-  for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
+  for (int item = first; item < it1; item += kEdgeWaves) {
     const int e = 4 * item + q;
     const bool valid = e < a.es.E;
-    int i = 0, j = 0;
-    EdgeIn in{0.0, 0.0, 0.0, 0.0};
-    if (valid) {
-      i = a.ei[e];
-      j = a.ej[e];
-      if (!a.init) in = edge_prefetch(a.es, e, pa);
+    const int ec = valid ? e : a.es.E - 1;
+    int i = i0, j = j0;
+    if (item != first) {
+      i = a.ei[ec];
+      j = a.ej[ec];
     }
+    // Groups of up to 8 passes (4 for FP64 rows), one group at a time.
+    // Loads are unconditional: lanes past the row end read feature 0 and
+    // their differences are dropped.  The bookkeeping loads follow the
+    // first group's row loads.
     double acc = 0.0;
-    if (valid) {
-      // groups of up to 4 passes: 8 row loads in flight per lane
-      constexpr int PG = NPASS < 4 ? NPASS : 4;
-#pragma unroll
+    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0};
+    {
+      constexpr int PGMAX = sizeof(TG) == 8 ? 4 : 8;
+      constexpr int PG = NPASS < PGMAX ? NPASS : PGMAX;
+      const TG *pi = Gc + (size_t)i * a.ld;
+      const TG *pj = Gc + (size_t)j * a.ld;
+#pragma unroll 1
       for (int pg = 0; pg < NPASS; pg += PG) {
         TG ri[PG][4], rj[PG][4];
 #pragma unroll
         for (int ps = 0; ps < PG; ++ps) {
           const int fo = (pg + ps) * 64 + l16 * 4;
-          if (fo < a.ld) {
-            RawIO<TG, 4>::load(Gc + (size_t)i * a.ld + fo, ri[ps]);
-            RawIO<TG, 4>::load(Gc + (size_t)j * a.ld + fo, rj[ps]);
-          } else {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) ri[ps][v] = rj[ps][v] = (TG)0;
-          }
+          const int fc = fo < a.ld ? fo : 0;
+          RawIO<TG, 4>::load(pi + fc, ri[ps]);
+          RawIO<TG, 4>::load(pj + fc, rj[ps]);
         }
+        if (pg == 0 && !a.init) in = edge_prefetch(a.es, ec);
 #pragma unroll
         for (int ps = 0; ps < PG; ++ps) {
+          const bool ok = (pg + ps) * 64 + l16 * 4 < a.ld;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double d = (double)ri[ps][v] - (double)rj[ps][v];
+            const double d = ok ? (double)ri[ps][v] - (double)rj[ps][v] : 0.0;
             acc = fma(d, d, acc);
           }
         }
@@ -773,7 +884,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_fused(EdgeArgs a) {
     if (valid && l16 == 0) edge_update(a.es, e, acc, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
-  edge_block_partials(t3, a.esum);
+  edge_block_partials(t3, pt, a.esum);
 }
 
 // Wide rows: one wave per (point i, 256-feature tile); each quarter-wave
@@ -783,7 +894,7 @@ template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_edge_tiles(EdgeArgs a) {
   using TG = typename Traits<PREC>::TG;
   constexpr int NPASS = 4;
-  DevScalars *sc = a.sc;
+  const DevScalars *sc = a.sc;
   if (!a.init && sc->done) return;
   const int pa = sc->pa;
   const int buf = a.init ? pa : (pa ^ 1);
@@ -849,7 +960,7 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
   constexpr int C4 = F / 4;
   extern __shared__ __align__(16) unsigned char smem[];
   TG *slab = reinterpret_cast<TG *>(smem);
-  DevScalars *sc = a.sc;
+  const DevScalars *sc = a.sc;
   if (!a.init && sc->done) return;
   const int pa = sc->pa;
   const int buf = a.init ? pa : (pa ^ 1);
@@ -903,22 +1014,28 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
 }
 
 // ------------------------------------------------------- k_edge_reduce
-// Wide rows: per edge, the tile partials in fixed order, then the same
-// per-edge bookkeeping and iteration finish as the fused edge kernel.
-__global__ __launch_bounds__(kBlock) void k_edge_reduce(ReduceArgs a) {
-  DevScalars *sc = a.sc;
+// Wide rows: one wave per edge sums the edge's tile partials (contiguous,
+// lane-strided, then the wave tree: a fixed order), then the same per-edge
+// bookkeeping as the fused edge kernel.
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_reduce(ReduceArgs a) {
+  const DevScalars *sc = a.sc;
   if (!a.init && sc->done) return;
+  const double pt = a.init ? 0.0 : gather_point_partials(a.psum, a.nbp);
   const int pa = sc->pa;
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   double t3[kEdgeSums] = {0.0, 0.0, 0.0};
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < a.es.E; e += gridDim.x * blockDim.x) {
+  for (int e = blockIdx.x * kEdgeWaves + wave; e < a.es.E; e += gridDim.x * kEdgeWaves) {
+    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!a.init && lane == 0) in = edge_prefetch(a.es, e);
+    const double *pe = a.part + (size_t)e * a.ntile;
     double nb2 = 0.0;
-    EdgeIn in{0.0, 0.0, 0.0, 0.0};
-    if (!a.init) in = edge_prefetch(a.es, e, pa);
-    for (int t = 0; t < a.ntile; ++t) nb2 += a.part[(size_t)e * a.ntile + t];
-    edge_update(a.es, e, nb2, in, a.init, pa, sc, t3);
+    for (int t = lane; t < a.ntile; t += kWave) nb2 += pe[t];
+    nb2 = wave_sum(nb2);
+    if (lane == 0) edge_update(a.es, e, nb2, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
-  edge_block_partials(t3, a.esum);
+  edge_block_partials(t3, pt, a.esum);
 }
 
 // --------------------------------------------------------- small kernels
@@ -930,7 +1047,7 @@ __global__ void k_set_params(DevScalars *sc, double mu, double rho, double eps,
   sc->m = 0; sc->done = 0; sc->converged = 0; sc->status = 0; sc->iters = 0;
   sc->d_prev = 0.0; sc->dA_prev = 0.0; sc->F_cur = 0.0;
   sc->F_last = 0.0; sc->d_last = 0.0; sc->rel_last = 0.0;
-  sc->counter = 0u;
+  sc->pending = 0;
 }
 
 __global__ void k_reset_scalars(DevScalars *sc) {
@@ -1115,22 +1232,28 @@ static hipEvent_t *prof_slot(Problem *P) {
   if (P->prof_every <= 0) return nullptr;
   const bool sample = (P->prof_iter++ % P->prof_every) == 0;
   if (!sample) return nullptr;
-  const size_t need = 4 * (P->prof_used + 1);
+  const size_t need = 3 * (P->prof_used + 1);
   while (P->prof_events.size() < need) {
     hipEvent_t ev;
     if (hipEventCreate(&ev) != hipSuccess) return nullptr;
     P->prof_events.push_back(ev);
   }
-  return &P->prof_events[4 * P->prof_used++];
+  return &P->prof_events[3 * P->prof_used++];
+}
+
+// Arguments of a point sweep: it reads the current scalar slot and writes the
+// other one.
+static PointArgs point_args(Problem *P, const Launch &Lp) {
+  return PointArgs{(int)P->n, (int)P->ld, P->ntile, Lp.nitems, Lp.chunk,
+                   P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
+                   P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_rho, P->cur_K,
+                   P->psum, P->esum, P->nbe, P->trace, P->sc + P->slot, P->sc + (P->slot ^ 1)};
 }
 
 template <int PREC, int VEC>
 static void launch_point_t(Problem *P, const Launch &Lp) {
-  PointArgs pa{(int)P->n, (int)P->ld, P->ntile, Lp.nitems, Lp.chunk,
-               P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
-               P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_rho, P->cur_K,
-               P->psum, P->sc};
-  hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kBlock), 0, P->stream, pa);
+  hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kBlock), 0, P->stream,
+                     point_args(P, Lp));
 }
 
 static EdgeState edge_state(Problem *P) {
@@ -1140,23 +1263,45 @@ static EdgeState edge_state(Problem *P) {
 static EdgeArgs edge_args(Problem *P, const Launch &Le, int init, int nbp) {
   return EdgeArgs{(int)P->n, (int)P->ld, P->entile, Le.nitems, Le.chunk, init, nbp,
                   P->G[0], P->G[1], P->ei, P->ej, P->rowptr, P->uptr, P->col, P->eid, P->part,
-                  edge_state(P), P->esum, P->psum, P->trace, P->sc};
+                  edge_state(P), P->esum, P->psum, P->sc + P->slot};
 }
 
-// Returns the number of blocks that wrote edge partials.
+// Grid of the fused edge kernel: groups of 4 edges, one per wave, at most
+// kEsumRows blocks (each leaves one partial row).
+static Launch edge_fused_grid(int64_t E) {
+  Launch L;
+  const int64_t nitems = std::max<int64_t>(cdiv(E, 4), 1);
+  L.nitems = (int)cdiv(E, 4);
+  int64_t blocks = std::min<int64_t>(cdiv(nitems, kEdgeWaves), kEsumRows);
+  blocks = std::min<int64_t>(cdiv(blocks, kXcds) * kXcds, kEsumRows);
+  L.blocks = (int)blocks;
+  L.chunk = (int)cdiv(nitems, blocks);
+  return L;
+}
+
+// Blocks of the edge-reduction kernel (wide rows): one wave per edge.
+static int edge_reduce_blocks(int64_t E) {
+  return (int)std::min<int64_t>(std::max<int64_t>(cdiv(E, kEdgeWaves), 1), kEsumRows);
+}
+
+// Partial rows the edge stage leaves for the next point sweep.
+static int edge_rows(Problem *P) {
+  return P->efused ? edge_fused_grid(P->E).blocks : edge_reduce_blocks(P->E);
+}
+
 template <int PREC>
-static int launch_edge_p(Problem *P, int init, int nbp) {
+static void launch_edge_p(Problem *P, int init, int nbp) {
   if (P->efused) {
-    const Launch Le = sweep_grid(cdiv(P->E, 4));
+    const Launch Le = edge_fused_grid(P->E);
     const EdgeArgs ea = edge_args(P, Le, init, nbp);
     switch (P->npass) {
-      case 1: hipLaunchKernelGGL((k_edge_fused<PREC, 1>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
-      case 2: hipLaunchKernelGGL((k_edge_fused<PREC, 2>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
-      case 4: hipLaunchKernelGGL((k_edge_fused<PREC, 4>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
-      case 8: hipLaunchKernelGGL((k_edge_fused<PREC, 8>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
-      default: hipLaunchKernelGGL((k_edge_fused<PREC, 16>), dim3(Le.blocks), dim3(kBlock), 0, P->stream, ea); break;
+      case 1: hipLaunchKernelGGL((k_edge_fused<PREC, 1>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      case 2: hipLaunchKernelGGL((k_edge_fused<PREC, 2>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      case 4: hipLaunchKernelGGL((k_edge_fused<PREC, 4>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      case 8: hipLaunchKernelGGL((k_edge_fused<PREC, 8>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      default: hipLaunchKernelGGL((k_edge_fused<PREC, 16>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
     }
-    return Le.blocks;
+    return;
   }
   if (P->eslab) {
     const Launch Ls{P->entile, 0, 0};
@@ -1173,18 +1318,14 @@ static int launch_edge_p(Problem *P, int init, int nbp) {
     hipLaunchKernelGGL((k_edge_tiles<PREC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream,
                        edge_args(P, Le, init, nbp));
   }
-  const int rblocks = (int)std::min<int64_t>(std::max<int64_t>(cdiv(P->E, kBlock), 1), kMaxBlocks);
-  ReduceArgs ra{P->entile, nbp, init, P->part, edge_state(P), P->esum, P->psum, P->trace, P->sc};
-  hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kBlock), 0, P->stream, ra);
-  return rblocks;
+  const int rblocks = edge_reduce_blocks(P->E);
+  ReduceArgs ra{P->entile, nbp, init, P->part, edge_state(P), P->esum, P->psum, P->sc + P->slot};
+  hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kEdgeBlock), 0, P->stream, ra);
 }
 
 template <int PREC, int F>
 static void launch_point_slab_t(Problem *P, int blocks) {
-  PointArgs pa{(int)P->n, (int)P->ld, P->ntile, 0, 0,
-               P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
-               P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_rho, P->cur_K,
-               P->psum, P->sc};
+  const PointArgs pa = point_args(P, Launch{blocks, 0, 0});
   const size_t lds = (size_t)P->n * F * sizeof(typename Traits<PREC>::TG);
   hipLaunchKernelGGL((k_point_slab<PREC, F>), dim3(blocks), dim3(kBlock), lds, P->stream, pa);
 }
@@ -1226,6 +1367,8 @@ static void launch_point_p(Problem *P, const Launch &Lp) {
   }
 }
 
+// One launch pair: the point sweep (which first finishes the pending
+// iteration) and the edge stage.  Advances the host's scalar slot.
 static void launch_iteration(Problem *P) {
   hipEvent_t *ev = prof_slot(P);
   if (ev) (void)hipEventRecord(ev[0], P->stream);
@@ -1234,22 +1377,19 @@ static void launch_iteration(Problem *P) {
   if (P->precision == kF32) launch_point_p<kF32>(P, Lp);
   else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
   else launch_point_p<kMixed>(P, Lp);
+  P->slot ^= 1;
   if (ev) (void)hipEventRecord(ev[1], P->stream);
-  int nbe;
-  if (P->precision == kF32) nbe = launch_edge_p<kF32>(P, 0, nbp);
-  else if (P->precision == kF64) nbe = launch_edge_p<kF64>(P, 0, nbp);
-  else nbe = launch_edge_p<kMixed>(P, 0, nbp);
+  if (P->precision == kF32) launch_edge_p<kF32>(P, 0, nbp);
+  else if (P->precision == kF64) launch_edge_p<kF64>(P, 0, nbp);
+  else launch_edge_p<kMixed>(P, 0, nbp);
   if (ev) (void)hipEventRecord(ev[2], P->stream);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, P->stream, (const double *)P->psum,
-                     nbp, (const double *)P->esum, nbe, P->trace, P->sc);
-  if (ev) (void)hipEventRecord(ev[3], P->stream);
 }
 
 // Edge norms of the A in buffer pa (state set or reset).
 static void launch_edge_init(Problem *P) {
-  if (P->precision == kF32) (void)launch_edge_p<kF32>(P, 1, 0);
-  else if (P->precision == kF64) (void)launch_edge_p<kF64>(P, 1, 0);
-  else (void)launch_edge_p<kMixed>(P, 1, 0);
+  if (P->precision == kF32) launch_edge_p<kF32>(P, 1, 0);
+  else if (P->precision == kF64) launch_edge_p<kF64>(P, 1, 0);
+  else launch_edge_p<kMixed>(P, 1, 0);
 }
 
 cc_status profile(Problem *P, int32_t sample_every) {
@@ -1265,8 +1405,8 @@ cc_status profile(Problem *P, int32_t sample_every) {
 // caller has synchronised the stream, so every event is complete.
 cc_status harvest_profile(Problem *P) {
   for (size_t k = 0; k < P->prof_used; ++k) {
-    hipEvent_t *ev = &P->prof_events[4 * k];
-    for (int q = 0; q < 3; ++q) {
+    hipEvent_t *ev = &P->prof_events[3 * k];
+    for (int q = 0; q < 2; ++q) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[q], ev[q + 1]) == hipSuccess) {
         P->prof_ms[q] += ms;
@@ -1454,8 +1594,9 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   CC_TRY(dmalloc((void **)&P->part, E * (P->efused ? 1 : P->entile) * 8));
   // one row of point partials per block of the point sweep
   CC_TRY(dmalloc((void **)&P->psum, std::max<int64_t>(kMaxBlocks, point_blocks(P)) * 8 * 8));
-  CC_TRY(dmalloc((void **)&P->esum, kMaxBlocks * 4 * 8));
-  CC_TRY(dmalloc((void **)&P->sc, sizeof(DevScalars)));
+  CC_TRY(dmalloc((void **)&P->esum, (size_t)kIterSums * kEsumRows * 8));
+  P->nbe = edge_rows(P);
+  CC_TRY(dmalloc((void **)&P->sc, 2 * sizeof(DevScalars)));
   CC_TRY(dmalloc((void **)&P->ncl_dev, 4));
   CC_HIP(hipHostMalloc((void **)&P->sc_host, sizeof(DevScalars), hipHostMallocDefault));
   CC_HIP(hipHostMalloc((void **)&P->flag_host, 64, hipHostMallocDefault));
@@ -1491,7 +1632,8 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   // ELL copy of the neighbour lists for the point sweep
   const int64_t S = std::max<int64_t>(maxdeg, 1);
   P->ell_s = (int)S;
-  std::vector<int32_t> hdegE(n), hcolE(n * S, 0), heidE(n * S, 0), hposE(2 * E);
+  // unused slots: column -1 (the wave sweep counts neighbours by it), edge 0
+  std::vector<int32_t> hdegE(n), hcolE(n * S, -1), heidE(n * S, 0), hposE(2 * E);
   // row-major (entry k of i at i*S + k) for the wave-per-point sweep,
   // column-major (k*n + i) for the slab sweep
   auto ell_slot = [&](int64_t i, int64_t k) -> int64_t { return P->ell_cm ? k * n + i : i * S + k; };
@@ -1605,6 +1747,7 @@ cc_status reset_state(Problem *P) {
     hipLaunchKernelGGL(k_fill, dim3((int)cdiv(P->E, 256)), dim3(256), 0, P->stream, P->s,
                        P->E, 1.0);
   }
+  P->slot = 0;
   hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, P->stream, P->sc);
   CC_HIP(hipGetLastError());
   launch_edge_init(P);
@@ -1615,7 +1758,7 @@ cc_status reset_state(Problem *P) {
 }
 
 static cc_status read_scalars(Problem *P) {
-  CC_HIP(hipMemcpyAsync(P->sc_host, P->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, P->stream));
+  CC_HIP(hipMemcpyAsync(P->sc_host, P->sc + P->slot, sizeof(DevScalars), hipMemcpyDeviceToHost, P->stream));
   CC_HIP(hipStreamSynchronize(P->stream));
   return CC_OK;
 }
@@ -1646,15 +1789,18 @@ cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info 
     }
   }
   const int record = o.record_objective ? 1 : 0;
-  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, P->stream, P->sc, gamma, rho, eps, thr,
-                     o.max_iter, record, o.test_every);
+  hipLaunchKernelGGL(k_set_params, dim3(1), dim3(1), 0, P->stream, P->sc + P->slot, gamma, rho,
+                     eps, thr, o.max_iter, record, o.test_every);
   CC_HIP(hipGetLastError());
   const int check = std::max(1, o.check_every);
-  for (int64_t it = 0; it <= (int64_t)o.max_iter; ++it) {
+  // sweeps m = 0 .. max_iter, each finished by the next launch pair; the
+  // last pair only finishes (the stop rule ends the solve by then)
+  const int64_t last = (int64_t)o.max_iter + 1;
+  for (int64_t it = 0; it <= last; ++it) {
     launch_iteration(P);
-    if ((it + 1) % check == 0 || it == (int64_t)o.max_iter) {
+    if ((it + 1) % check == 0 || it == last) {
       CC_HIP(hipGetLastError());
-      CC_HIP(hipMemcpyAsync(P->flag_host, &P->sc->done, 4, hipMemcpyDeviceToHost, P->stream));
+      CC_HIP(hipMemcpyAsync(P->flag_host, &P->sc[P->slot].done, 4, hipMemcpyDeviceToHost, P->stream));
       CC_HIP(hipStreamSynchronize(P->stream));
       if (P->prof_used) harvest_profile(P);
       if (P->flag_host[0]) break;
@@ -1751,6 +1897,7 @@ cc_status set_state(Problem *P, const double *U, const double *A, int64_t ld, co
   else
     hipLaunchKernelGGL((k_set_rows<kMixed>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (int)P->ld, U, A, ld, P->U, P->A[0], P->G[0]);
   if (P->E > 0) CC_HIP(hipMemcpyAsync(P->s, s, P->E * 8, hipMemcpyDeviceToDevice, P->stream));
+  P->slot = 0;
   hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, P->stream, P->sc);
   CC_HIP(hipGetLastError());
   launch_edge_init(P);
