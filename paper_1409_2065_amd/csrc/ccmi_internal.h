@@ -14,6 +14,8 @@ namespace ccmi {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kPointWaves = 4;  // waves per block of the wave-per-item point sweep
+constexpr int kPointBlock = kWave * kPointWaves;
 constexpr int kXcds = 8;         // MI355X: 8 accelerator complex dies
 constexpr int kMaxBlocks = 2048; // grid cap for the grid-stride sweeps
 constexpr int kPointSums = 6;    // per-block FP64 partial sums of the point pass
@@ -21,7 +23,9 @@ constexpr int kEdgeSums = 3;     // per-block FP64 partial sums of the edge pass
 constexpr int kIterSums = kPointSums + kEdgeSums;
 constexpr int kEdgeBlock = 1024; // threads per block of the edge-stage kernels
 constexpr int kEdgeWaves = kEdgeBlock / kWave;
-constexpr int kEsumRows = 512;   // partial rows the edge stage leaves (column-major)
+constexpr int kEsumRows = 512;   // max partial rows the edge stage leaves
+constexpr int kEsumStride = 10;  // doubles per partial row (kIterSums, padded to 16 B)
+constexpr int kItemEdges = 8;    // edges per work item of the item edge sweep
 
 // Device-resident iteration scalars, in two slots.  Written by the host
 // only through the set-parameters and reset kernels.  A point sweep reads
@@ -56,6 +60,9 @@ struct Problem {
   int entile = 1;     // edge-sweep tiles (1: the fused edge kernel)
   int npass = 4;      // 64-feature passes per edge tile
   bool efused = true;
+  bool eitems = false;       // rows up to 512 wide: edge work items by lower end
+  int item_nv = 8;           // features per lane of the item edge sweep
+  int64_t n_items = 0;       // edge work items (up to kItemEdges edges each)
   bool eslab = false;        // wide rows, small n: LDS-slab edge sweep
   int eslab_tpg = 1;         // feature tiles per block of the slab edge sweep
   int eslab_ntf = 1;         // feature tiles of width edge_f
@@ -69,6 +76,8 @@ struct Problem {
   void *Usnap = nullptr, *Asnap = nullptr;  // stop-test window snapshots
   int32_t *rowptr = nullptr, *col = nullptr, *eid = nullptr, *uptr = nullptr;
   int32_t *ei = nullptr, *ej = nullptr;
+  int32_t *itemI = nullptr;  // lower end of each edge work item
+  int32_t *itemJ = nullptr, *itemE = nullptr;  // kItemEdges upper ends / edge ids per item (-1 pad)
   double *w = nullptr, *s = nullptr, *nb[2] = {nullptr, nullptr};
   double *qe = nullptr;     // mu w / (rho ||b||) per edge
   // point-sweep neighbour lists, fixed stride ell_s per point (ELL layout):
@@ -83,8 +92,8 @@ struct Problem {
   int cur_K = 64;
   double *part = nullptr;    // E x entile edge partials
   double *psum = nullptr;    // point-sweep blocks x 8 point partials
-  double *esum = nullptr;    // kIterSums x kEsumRows, column-major: partial
-                             // rows of the edge stage (point sums gathered in)
+  double *esum = nullptr;    // kEsumRows x kEsumStride: partial rows of the
+                             // edge stage (point sums gathered in)
   int nbe = 1;               // partial rows the edge stage writes
   double *trace = nullptr;   // objective per iteration (record mode)
   int64_t trace_cap = 0, trace_count = 0;

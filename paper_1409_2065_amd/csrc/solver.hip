@@ -180,7 +180,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Fixed-order block reduction of NV doubles per thread; result valid in
-// thread 0.  Uses a shared scratch of kWavesPerBlock * NV doubles.
+// thread 0.  Uses a shared scratch of (waves per block) * NV doubles.
 template <int NV>
 __device__ inline void block_sum(double (&v)[NV], double *scratch) {
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -202,10 +202,10 @@ __device__ inline void block_sum(double (&v)[NV], double *scratch) {
   __syncthreads();
 }
 
-// Fixed-order block reduction whose result every thread receives (the xor
-// butterfly leaves the same value in every lane; the NW waves are then
-// summed in order).  scratch: NW * NV doubles, not reused by the caller
-// before its next barrier.
+// Fixed-order block reduction whose result every thread receives: wave
+// trees, then thread q sums value q over the NW waves in order and the
+// totals are broadcast through LDS.  scratch: (NW + 1) * NV doubles, not
+// reused by the caller before its next barrier.
 template <int NV, int NW>
 __device__ inline void block_sum_all(double (&v)[NV], double *scratch) {
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -216,13 +216,15 @@ __device__ inline void block_sum_all(double (&v)[NV], double *scratch) {
     for (int q = 0; q < NV; ++q) scratch[wave * NV + q] = v[q];
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
+  if (threadIdx.x < NV) {
     double acc = 0.0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) acc += scratch[w * NV + q];
-    v[q] = acc;
+    for (int w = 0; w < NW; ++w) acc += scratch[w * NV + threadIdx.x];
+    scratch[NW * NV + threadIdx.x] = acc;
   }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = scratch[NW * NV + q];
 }
 
 // Logical block index: physical block b runs on XCD b % 8 (round-robin
@@ -271,6 +273,7 @@ struct EdgeArgs {
   int n, ld, ntile, nitems, chunk, init, nbp;
   const void *G0, *G1;
   const int32_t *ei, *ej;
+  const int32_t *itemI, *itemJ, *itemE;  // edge work items (item sweep)
   const int32_t *rowptr, *uptr, *col, *eid;  // CSR (wide-row tiles)
   double *part;         // E x ntile partial ||b||^2 (ntile > 1)
   EdgeState es;
@@ -333,21 +336,30 @@ __device__ inline void finish_scalars(DevScalars &h, const double (&v)[kIterSums
 // Start of a point sweep: when a sweep is pending, sum the edge stage's
 // partial rows (column-major, the same order in every block) and finish its
 // iteration; block 0 stores the scalars of the iteration about to run (or
-// the final ones) in the other slot.  Blocks of kBlock threads; red:
-// kWavesPerBlock * kIterSums.
+// the final ones) in the other slot.  Blocks of NW waves; red:
+// (NW + 1) * kIterSums.
+template <int NW>
 __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red) {
   double v[kIterSums];
 #pragma unroll
   for (int q = 0; q < kIterSums; ++q) v[q] = 0.0;
-  // issued before the scalars are known; unused when nothing is pending
-  for (int b = threadIdx.x; b < a.nrows; b += kBlock) {
+  // issued before the scalars are known; unused when nothing is pending.
+  // A row is 5 aligned 16-byte loads.
+  for (int b = threadIdx.x; b < a.nrows; b += NW * kWave) {
+    const double2 *r = reinterpret_cast<const double2 *>(a.esum + (size_t)b * kEsumStride);
+    double2 t[kEsumStride / 2];
 #pragma unroll
-    for (int q = 0; q < kIterSums; ++q) v[q] += a.esum[(size_t)q * kEsumRows + b];
+    for (int k = 0; k < kEsumStride / 2; ++k) t[k] = r[k];
+#pragma unroll
+    for (int k = 0; k < kEsumStride / 2; ++k) {
+      v[2 * k] += t[k].x;
+      if (2 * k + 1 < kIterSums) v[2 * k + 1] += t[k].y;
+    }
   }
   DevScalars h = *a.sin;
   const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
   if (h.pending && !h.done) {  // uniform
-    block_sum_all<kIterSums, kWavesPerBlock>(v, red);
+    block_sum_all<kIterSums, NW>(v, red);
     finish_scalars(h, v, a.trace, writer);
   }
   h.pending = h.done ? 0 : 1;
@@ -357,12 +369,12 @@ __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red) {
 
 // ------------------------------------------------------------- k_point
 template <int PREC, int VEC>
-__global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
+__global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
   using TS = typename Traits<PREC>::TS;
   using TG = typename Traits<PREC>::TG;
   using TX = typename Traits<PREC>::TX;
-  __shared__ double scratch[kWavesPerBlock * kPointSums];
-  __shared__ double red[kWavesPerBlock * kIterSums];
+  __shared__ double scratch[kPointWaves * kPointSums];
+  __shared__ double red[(kPointWaves + 1) * kIterSums];
   const TX *X = reinterpret_cast<const TX *>(a.X);
   TS *U = reinterpret_cast<TS *>(a.U);
   const int lane = threadIdx.x % kWave;
@@ -393,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
     RawIO<TX, VEC>::load(X + rowc, x0);
   }
 
-  const DevScalars hs = begin_iteration(a, red);
+  const DevScalars hs = begin_iteration<kPointWaves>(a, red);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
   const double rho = a.rho, dprev = hs.d_prev;
@@ -411,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_point(PointArgs a) {
   TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
   double ps[kPointSums] = {0, 0, 0, 0, 0, 0};
 
-  for (int item = first; item < it1; item += kWavesPerBlock) {
+  for (int item = first; item < it1; item += kPointWaves) {
     const int t = item / a.n, i = item - t * a.n;
     const int f0 = t * W + lane * VEC;
     const bool active = f0 < a.ld;
@@ -604,8 +616,8 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   TG *slab = reinterpret_cast<TG *>(smem);
   __shared__ double scratch[kWavesPerBlock * kPointSums];
-  __shared__ double red[kWavesPerBlock * kIterSums];
-  const DevScalars hs = begin_iteration(a, red);
+  __shared__ double red[(kWavesPerBlock + 1) * kIterSums];
+  const DevScalars hs = begin_iteration<kWavesPerBlock>(a, red);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
   const double rho = a.rho, dprev = hs.d_prev;
@@ -753,10 +765,11 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
 // before the row gathers are issued.
 struct EdgeIn {
   double qprev, n0, n1, w, s;
+  int p0, p1;  // ELL positions of the two directions
 };
 
 __device__ inline EdgeIn edge_prefetch(const EdgeState &es, int e) {
-  return EdgeIn{es.qe[e], es.nb0[e], es.nb1[e], es.w[e], es.s[e]};
+  return EdgeIn{es.qe[e], es.nb0[e], es.nb1[e], es.w[e], es.s[e], es.epos[2 * e], es.epos[2 * e + 1]};
 }
 
 // Given ||b_e||^2 of the new A_m: store ||b_e||; in an iteration also take
@@ -778,28 +791,49 @@ __device__ inline void edge_update(const EdgeState &es, int e, double nb2, const
   t3[2] += in.w * sv * np;
   const double q = (nbn > 0.0) ? (sc->mu * in.w) / (sc->rho * nbn) : __builtin_inf();
   es.qe[e] = q;
-  es.qE[es.epos[2 * e]] = q;
-  es.qE[es.epos[2 * e + 1]] = q;
+  es.qE[in.p0] = q;
+  es.qE[in.p1] = q;
 }
 
 // Partial row of an edge-stage block: the point-sweep partials of rows
-// blockIdx.x, blockIdx.x + gridDim.x, ... (pt, held by threads 0..5) and the
-// block's edge sums, stored column-major for the next point sweep.
-__device__ inline double gather_point_partials(const double *psum, int nbp) {
+// blockIdx.x, blockIdx.x + gridDim.x, ... summed in that order (pt, held by
+// threads 0..5) and the block's edge sums, stored as one padded row for the
+// next point sweep.  The point partials of the first kGatherRows rows are
+// loaded at the start of the kernel, one value per thread, and summed at
+// the end through LDS.
+static_assert(kEsumStride % 2 == 0 && kEsumStride > kIterSums, "partial row layout");
+constexpr int kGatherRows = 8;
+
+__device__ inline double point_partial_load(const double *psum, int nbp) {
+  const int k = threadIdx.x / kPointSums, q = threadIdx.x - k * kPointSums;
+  const int r = blockIdx.x + k * gridDim.x;
+  return (k < kGatherRows && r < nbp) ? psum[(size_t)r * 8 + q] : 0.0;
+}
+
+// Needs blocks of at least kGatherRows * kPointSums threads; a barrier.
+__device__ inline double point_partial_sum(double mine, const double *psum, int nbp) {
+  __shared__ double rows[kGatherRows * kPointSums];
+  if (threadIdx.x < kGatherRows * kPointSums) rows[threadIdx.x] = mine;
+  __syncthreads();
   double pt = 0.0;
   if (threadIdx.x < kPointSums) {
-    for (int r = blockIdx.x; r < nbp; r += gridDim.x) pt += psum[(size_t)r * 8 + threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < kGatherRows; ++k) pt += rows[k * kPointSums + threadIdx.x];
+    for (int r = blockIdx.x + kGatherRows * gridDim.x; r < nbp; r += gridDim.x)
+      pt += psum[(size_t)r * 8 + threadIdx.x];
   }
   return pt;
 }
 
 __device__ inline void edge_block_partials(double (&t3)[kEdgeSums], double pt, double *esum) {
   __shared__ double red[kEdgeWaves * kEdgeSums];
+  double *row = esum + (size_t)blockIdx.x * kEsumStride;
+  if (threadIdx.x < kPointSums) row[threadIdx.x] = pt;
   block_sum<kEdgeSums>(t3, red);
-  if (threadIdx.x < kPointSums) esum[(size_t)threadIdx.x * kEsumRows + blockIdx.x] = pt;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < kEdgeSums; ++q) esum[(size_t)(kPointSums + q) * kEsumRows + blockIdx.x] = t3[q];
+    for (int q = 0; q < kEdgeSums; ++q) row[kPointSums + q] = t3[q];
+    row[kIterSums] = 0.0;  // padding
   }
 }
 
@@ -829,7 +863,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
     j0 = a.ej[ec];
   }
   if (!a.init && sc->done) return;
-  const double pt = a.init ? 0.0 : gather_point_partials(a.psum, a.nbp);
+  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp);
   const int pa = sc->pa;
   // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
   const int buf = a.init ? pa : (pa ^ 1);
@@ -844,14 +878,15 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
       i = a.ei[ec];
       j = a.ej[ec];
     }
-    // Groups of up to 8 passes (4 for FP64 rows), one group at a time.
+    // Groups of up to 8 passes (4 for FP64 rows and 1024-wide rows), one
+    // group at a time.
     // Loads are unconditional: lanes past the row end read feature 0 and
     // their differences are dropped.  The bookkeeping loads follow the
     // first group's row loads.
     double acc = 0.0;
-    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0};
+    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0};
     {
-      constexpr int PGMAX = sizeof(TG) == 8 ? 4 : 8;
+      constexpr int PGMAX = (sizeof(TG) == 8 || NPASS > 8) ? 4 : 8;
       constexpr int PG = NPASS < PGMAX ? NPASS : PGMAX;
       const TG *pi = Gc + (size_t)i * a.ld;
       const TG *pj = Gc + (size_t)j * a.ld;
@@ -884,7 +919,93 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
     if (valid && l16 == 0) edge_update(a.es, e, acc, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
-  edge_block_partials(t3, pt, a.esum);
+  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp), a.esum);
+}
+
+// Rows up to 512 wide: one wave per work item of up to kItemEdges edges
+// (i, j_q) sharing the lower end i (lists built on the host).  Row i of the
+// new A is loaded once, NV features per lane (the whole row across the
+// wave), and the rows j_q in one batch; each ||a_i - a_j||^2 is a wave sum
+// and lane q finishes edge q.  Per edge one row is gathered instead of two.
+template <int PREC, int NV>
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_items(EdgeArgs a) {
+  using TG = typename Traits<PREC>::TG;
+  constexpr int CH = NV < 4 ? NV : 4;  // features per load
+  constexpr int NCH = NV / CH;
+  const DevScalars *sc = a.sc;
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lb = logical_block();
+  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
+  // the first item's lists are loaded before the scalars: both arrive together
+  const int first = it0 + wave;
+  int jl0 = -1, el0 = -1, i0 = 0;
+  if (first < it1) {
+    if (lane < kItemEdges) {
+      jl0 = a.itemJ[(size_t)first * kItemEdges + lane];
+      el0 = a.itemE[(size_t)first * kItemEdges + lane];
+    }
+    i0 = a.itemI[first];
+  }
+  if (!a.init && sc->done) return;
+  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp);
+  const int pa = sc->pa;
+  // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
+  const int buf = a.init ? pa : (pa ^ 1);
+  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
+  double t3[kEdgeSums] = {0.0, 0.0, 0.0};
+  for (int item = first; item < it1; item += kEdgeWaves) {
+    int jl = jl0, el = el0, i = i0;
+    if (item != first) {
+      jl = -1;
+      el = -1;
+      if (lane < kItemEdges) {
+        jl = a.itemJ[(size_t)item * kItemEdges + lane];
+        el = a.itemE[(size_t)item * kItemEdges + lane];
+      }
+      i = a.itemI[item];
+    }
+    i = __builtin_amdgcn_readfirstlane(i);
+    // Loads are unconditional: a chunk past the row end reads feature 0 and
+    // is dropped, an unused slot reads row i and is not stored.
+    TG gi[NCH][CH], rj[kItemEdges][NCH][CH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int fo = lane * NV + c * CH;
+      RawIO<TG, CH>::load(Gc + (size_t)i * a.ld + (fo < a.ld ? fo : 0), gi[c]);
+    }
+#pragma unroll
+    for (int q = 0; q < kItemEdges; ++q) {
+      const int jq = __builtin_amdgcn_readlane(jl, q);
+      const size_t rowq = (size_t)(jq >= 0 ? jq : i) * a.ld;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int fo = lane * NV + c * CH;
+        RawIO<TG, CH>::load(Gc + rowq + (fo < a.ld ? fo : 0), rj[q][c]);
+      }
+    }
+    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0};
+    if (!a.init && el >= 0) in = edge_prefetch(a.es, el);
+    double mine = 0.0;
+#pragma unroll
+    for (int q = 0; q < kItemEdges; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const bool ok = lane * NV + c * CH < a.ld;
+#pragma unroll
+        for (int v = 0; v < CH; ++v) {
+          const double d = ok ? (double)gi[c][v] - (double)rj[q][c][v] : 0.0;
+          acc = fma(d, d, acc);
+        }
+      }
+      acc = wave_sum(acc);
+      mine = (lane == q) ? acc : mine;
+    }
+    if (el >= 0) edge_update(a.es, el, mine, in, a.init, pa, sc, t3);
+  }
+  if (a.init) return;
+  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp), a.esum);
 }
 
 // Wide rows: one wave per (point i, 256-feature tile); each quarter-wave
@@ -1020,13 +1141,13 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
 __global__ __launch_bounds__(kEdgeBlock) void k_edge_reduce(ReduceArgs a) {
   const DevScalars *sc = a.sc;
   if (!a.init && sc->done) return;
-  const double pt = a.init ? 0.0 : gather_point_partials(a.psum, a.nbp);
+  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp);
   const int pa = sc->pa;
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   double t3[kEdgeSums] = {0.0, 0.0, 0.0};
   for (int e = blockIdx.x * kEdgeWaves + wave; e < a.es.E; e += gridDim.x * kEdgeWaves) {
-    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0};
+    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0};
     if (!a.init && lane == 0) in = edge_prefetch(a.es, e);
     const double *pe = a.part + (size_t)e * a.ntile;
     double nb2 = 0.0;
@@ -1035,7 +1156,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_reduce(ReduceArgs a) {
     if (lane == 0) edge_update(a.es, e, nb2, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
-  edge_block_partials(t3, pt, a.esum);
+  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp), a.esum);
 }
 
 // --------------------------------------------------------- small kernels
@@ -1214,12 +1335,13 @@ struct Launch {
   int blocks, chunk, nitems;
 };
 
-// Grid for a sweep over nitems wave-items: at most kMaxBlocks blocks, a
-// multiple of the XCD count, each block owning a contiguous chunk.
-static Launch sweep_grid(int64_t nitems) {
+// Grid for a sweep over nitems wave-items with `waves` waves per block: at
+// most kMaxBlocks blocks, a multiple of the XCD count, each block owning a
+// contiguous chunk.
+static Launch sweep_grid(int64_t nitems, int waves = kWavesPerBlock) {
   Launch L;
   L.nitems = (int)nitems;
-  int64_t want = cdiv(std::max<int64_t>(nitems, 1), kWavesPerBlock);
+  int64_t want = cdiv(std::max<int64_t>(nitems, 1), waves);
   int64_t blocks = std::min<int64_t>(want, kMaxBlocks);
   blocks = cdiv(blocks, kXcds) * kXcds;
   L.blocks = (int)blocks;
@@ -1252,7 +1374,7 @@ static PointArgs point_args(Problem *P, const Launch &Lp) {
 
 template <int PREC, int VEC>
 static void launch_point_t(Problem *P, const Launch &Lp) {
-  hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kBlock), 0, P->stream,
+  hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream,
                      point_args(P, Lp));
 }
 
@@ -1262,7 +1384,8 @@ static EdgeState edge_state(Problem *P) {
 
 static EdgeArgs edge_args(Problem *P, const Launch &Le, int init, int nbp) {
   return EdgeArgs{(int)P->n, (int)P->ld, P->entile, Le.nitems, Le.chunk, init, nbp,
-                  P->G[0], P->G[1], P->ei, P->ej, P->rowptr, P->uptr, P->col, P->eid, P->part,
+                  P->G[0], P->G[1], P->ei, P->ej, P->itemI, P->itemJ, P->itemE,
+                  P->rowptr, P->uptr, P->col, P->eid, P->part,
                   edge_state(P), P->esum, P->psum, P->sc + P->slot};
 }
 
@@ -1279,6 +1402,18 @@ static Launch edge_fused_grid(int64_t E) {
   return L;
 }
 
+// Grid of the item edge kernel: one item per wave, at most kEsumRows blocks.
+static Launch edge_items_grid(int64_t n_items) {
+  Launch L;
+  const int64_t nitems = std::max<int64_t>(n_items, 1);
+  L.nitems = (int)n_items;
+  int64_t blocks = std::min<int64_t>(cdiv(nitems, kEdgeWaves), kEsumRows);
+  blocks = std::min<int64_t>(cdiv(blocks, kXcds) * kXcds, kEsumRows);
+  L.blocks = (int)blocks;
+  L.chunk = (int)cdiv(nitems, blocks);
+  return L;
+}
+
 // Blocks of the edge-reduction kernel (wide rows): one wave per edge.
 static int edge_reduce_blocks(int64_t E) {
   return (int)std::min<int64_t>(std::max<int64_t>(cdiv(E, kEdgeWaves), 1), kEsumRows);
@@ -1286,11 +1421,27 @@ static int edge_reduce_blocks(int64_t E) {
 
 // Partial rows the edge stage leaves for the next point sweep.
 static int edge_rows(Problem *P) {
+  if (P->eitems) return edge_items_grid(P->n_items).blocks;
   return P->efused ? edge_fused_grid(P->E).blocks : edge_reduce_blocks(P->E);
 }
 
 template <int PREC>
 static void launch_edge_p(Problem *P, int init, int nbp) {
+  if (P->eitems) {
+    const Launch Li = edge_items_grid(P->n_items);
+    const EdgeArgs ea = edge_args(P, Li, init, nbp);
+    switch (P->item_nv) {
+      case 1: hipLaunchKernelGGL((k_edge_items<PREC, 1>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      case 2: hipLaunchKernelGGL((k_edge_items<PREC, 2>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      case 4: hipLaunchKernelGGL((k_edge_items<PREC, 4>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      default:
+        // FP64 rows take at most 4 features per lane (register budget)
+        if constexpr (PREC != kF64)
+          hipLaunchKernelGGL((k_edge_items<PREC, 8>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea);
+        break;
+    }
+    return;
+  }
   if (P->efused) {
     const Launch Le = edge_fused_grid(P->E);
     const EdgeArgs ea = edge_args(P, Le, init, nbp);
@@ -1345,7 +1496,7 @@ static void set_slab_attr() {
 // Blocks of the point sweep (its partials count).
 static int point_blocks(Problem *P) {
   if (P->slab_f > 0) return (int)(cdiv(P->ntile * cdiv(P->n, kBlock), kXcds) * kXcds);
-  return sweep_grid(P->n * P->ntile).blocks;
+  return sweep_grid(P->n * P->ntile, kPointWaves).blocks;
 }
 
 template <int PREC>
@@ -1372,7 +1523,7 @@ static void launch_point_p(Problem *P, const Launch &Lp) {
 static void launch_iteration(Problem *P) {
   hipEvent_t *ev = prof_slot(P);
   if (ev) (void)hipEventRecord(ev[0], P->stream);
-  const Launch Lp = sweep_grid(P->n * P->ntile);
+  const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves);
   const int nbp = point_blocks(P);
   if (P->precision == kF32) launch_point_p<kF32>(P, Lp);
   else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
@@ -1421,6 +1572,7 @@ cc_status harvest_profile(Problem *P) {
 void problem_free(Problem *P) {
   if (!P) return;
   void *bufs[] = {P->X, P->M, P->U, P->A[0], P->A[1], P->Usnap, P->Asnap, P->rowptr, P->col, P->eid, P->uptr,
+                  P->itemI, P->itemJ, P->itemE,
                   P->ei, P->ej, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qE, P->epos, P->degE, P->colE,
                   P->eidE, P->part, P->psum,
                   P->esum, P->trace, P->sc, P->ncl_dev};
@@ -1480,7 +1632,15 @@ static void choose_tiles(Problem *P) {
   P->vec = vec;
   P->tile_w = slab > 0 ? slab : kWave * vec;
   P->ntile = (int)cdiv(P->ld, P->tile_w);
-  // edge sweep: one tile over the whole row when it is at most 1024 wide
+  // edge sweep: work items of edges sharing a lower end when the whole row
+  // fits a wave at 8 features per lane (4 for FP64 rows; CCMI_EDGE_ITEMS=0
+  // turns this off), else one tile over the whole row when it is at most
+  // 1024 wide
+  const char *eit = getenv("CCMI_EDGE_ITEMS");
+  const int64_t item_w = (P->precision == kF64 ? 4 : 8) * kWave;
+  P->eitems = P->ld <= item_w && !(eit && atoi(eit) == 0);
+  P->item_nv = 1;
+  while (P->item_nv * kWave < P->ld) P->item_nv <<= 1;
   if (P->ld <= 1024) {
     int np = 1;
     while (64 * np < P->ld) np <<= 1;
@@ -1594,8 +1754,7 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   CC_TRY(dmalloc((void **)&P->part, E * (P->efused ? 1 : P->entile) * 8));
   // one row of point partials per block of the point sweep
   CC_TRY(dmalloc((void **)&P->psum, std::max<int64_t>(kMaxBlocks, point_blocks(P)) * 8 * 8));
-  CC_TRY(dmalloc((void **)&P->esum, (size_t)kIterSums * kEsumRows * 8));
-  P->nbe = edge_rows(P);
+  CC_TRY(dmalloc((void **)&P->esum, (size_t)kEsumRows * kEsumStride * 8));
   CC_TRY(dmalloc((void **)&P->sc, 2 * sizeof(DevScalars)));
   CC_TRY(dmalloc((void **)&P->ncl_dev, 4));
   CC_HIP(hipHostMalloc((void **)&P->sc_host, sizeof(DevScalars), hipHostMallocDefault));
@@ -1629,6 +1788,32 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
     maxdeg = std::max<int64_t>(maxdeg, rp[i + 1] - rp[i]);
   }
   P->max_deg = maxdeg;
+  // edge work items: the upper neighbours of each point in runs of up to
+  // kItemEdges (unused slots -1)
+  {
+    std::vector<int32_t> iI, iJ, iE;
+    for (int64_t i = 0; i < n; ++i) {
+      for (int32_t k = hup[i]; k < rp[i + 1]; k += kItemEdges) {
+        iI.push_back((int32_t)i);
+        for (int q = 0; q < kItemEdges; ++q) {
+          const bool ok = k + q < rp[i + 1];
+          iJ.push_back(ok ? hcol[k + q] : -1);
+          iE.push_back(ok ? heid[k + q] : -1);
+        }
+      }
+    }
+    P->n_items = (int64_t)iI.size();
+    CC_TRY(dmalloc((void **)&P->itemI, iI.size() * 4));
+    CC_TRY(dmalloc((void **)&P->itemJ, iJ.size() * 4));
+    CC_TRY(dmalloc((void **)&P->itemE, iE.size() * 4));
+    if (!iI.empty()) {
+      CC_HIP(hipMemcpyAsync(P->itemI, iI.data(), iI.size() * 4, hipMemcpyHostToDevice, stream));
+      CC_HIP(hipMemcpyAsync(P->itemJ, iJ.data(), iJ.size() * 4, hipMemcpyHostToDevice, stream));
+      CC_HIP(hipMemcpyAsync(P->itemE, iE.data(), iE.size() * 4, hipMemcpyHostToDevice, stream));
+      CC_HIP(hipStreamSynchronize(stream));  // the host vectors go out of scope
+    }
+  }
+  P->nbe = edge_rows(P);
   // ELL copy of the neighbour lists for the point sweep
   const int64_t S = std::max<int64_t>(maxdeg, 1);
   P->ell_s = (int)S;

@@ -252,6 +252,25 @@ def test_wide_rows_edge_tiles(cc, precision, tol):
     assert rel_max(A, st.A) < tol
 
 
+@pytest.mark.parametrize("p,precision,items", [
+    (40, "f64", "1"), (100, "f64", "1"), (200, "f64", "1"), (200, "f64", "0"),
+    (450, "mixed", "1"), (450, "mixed", "0"), (700, "mixed", "1")])
+def test_edge_sweep_variants(cc, p, precision, items, monkeypatch):
+    """Edge sweep by work items of edges sharing a lower end (1, 2, 4 and 8
+    features per lane), its edge-parallel fallback (CCMI_EDGE_ITEMS=0) and
+    the edge-parallel kernel for rows up to 1024 wide follow the oracle's
+    trajectory."""
+    monkeypatch.setenv("CCMI_EDGE_ITEMS", items)
+    X, M, E, w, _ = reduced_expression(n=150, p=p)
+    st, _ = oracle_jacobi(X, M, E, w).solve(3.0, mm.Opts(tol=0, max_iter=60, proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, precision) as g:
+        g.solve(3.0, tol=0.0, max_iter=60)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    tol = 1e-11 if precision == "f64" else 2e-6
+    assert rel_max(U, st.U) < tol
+    assert rel_max(A, st.A) < tol
+
+
 @pytest.mark.parametrize("edge_slab", ["0", "1"])
 def test_wide_rows_edge_variants(cc, edge_slab, monkeypatch):
     """Wide rows: the per-tile edge partials (CCMI_EDGE_SLAB=0) and the LDS
