@@ -72,6 +72,7 @@ enum { CC_DTYPE_F32 = 0, CC_DTYPE_F64 = 1 };
 enum { CC_PREC_F32 = 0, CC_PREC_MIXED = 1, CC_PREC_F64 = 2 };
 
 typedef struct cc_problem *cc_problem_t;
+typedef struct cc_batch *cc_batch_t;
 
 /* Solver options.  Fill with cc_default_opts() and then change fields.
  *   eta         accuracy knob: eps = (eta * rho)^2 when eps <= 0.  The MM
@@ -279,6 +280,51 @@ cc_status cc_standardize_columns(int64_t n, int64_t p, int32_t x_dtype,
 cc_status cc_components(int64_t n, int64_t n_edges, const int32_t *ei,
                         const int32_t *ej, const uint8_t *keep,
                         int32_t *labels, int32_t *n_components, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Batched solves
+ * ---------------------------------------------------------------------
+ * Many independent problems, each along its own gamma path (Methods: the
+ * solution path over the regularisation parameter, with warm starts), run
+ * in the same launches: per MM iteration one point-sweep and one edge-sweep
+ * launch cover every instance, and each instance keeps its own rho, eps, d,
+ * objective and stopping test, and moves to its next gamma on the device.
+ *
+ * cc_batch_create: problems[0..n_inst-1] (host array of handles, distinct,
+ * same precision, p <= 512, or p <= 256 in FP64); n_gamma (host, n_inst
+ * entries >= 1) and gammas (host, the paths one after another, each value
+ * finite and >= 0).  opts may be NULL (defaults); each gamma is solved as
+ * cc_solve would with these options, warm-started from the previous one
+ * (the first from the problem's current state).  autotune != 0 times a few
+ * iterations of each point-sweep tile width (64, 128, 256 features) and
+ * keeps the fastest; it leaves every problem at its initial state.  The
+ * batch refers to the problems (it does not own them): destroy the batch
+ * first.  A problem's solver state belongs to the batch while it runs.
+ *
+ * cc_batch_run: runs every path to its end and waits for it.  labels
+ * (device int32, may be NULL): for each instance in order, n_gamma[b] rows
+ * of n_b labels as cc_solve_path writes them.  infos (host, sum of n_gamma
+ * entries, may be NULL): per (instance, gamma) as cc_solve fills them, with
+ * seconds = time from the start of the run to the end of that gamma.
+ * latency_ms (host, n_inst entries, may be NULL): time from the start of
+ * the run to the end of each instance's path.  Afterwards each problem's
+ * state is the final state of its path (cc_get_U etc. read it).
+ * Returns CC_ERR_NUMERIC if any instance's d or objective became
+ * non-finite (its path stops there; the others finish).
+ *
+ * cc_batch_config: the chosen point-sweep features per lane (vec: tile
+ * width 64 * vec), the MM iterations per graph replay, and (tune_us, host,
+ * 3 entries, may be NULL) the autotuner's microseconds per iteration for
+ * vec = 1, 2, 4 (zeros without autotuning). */
+cc_status cc_batch_create(int32_t n_inst, const cc_problem_t *problems,
+                          const int32_t *n_gamma, const double *gammas,
+                          const cc_solve_opts *opts, int32_t autotune,
+                          cc_batch_t *out);
+cc_status cc_batch_run(cc_batch_t batch, int32_t *labels, cc_solve_info *infos,
+                       double *latency_ms);
+cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *graph_iters,
+                          double *tune_us);
+cc_status cc_batch_destroy(cc_batch_t batch);
 
 #ifdef __cplusplus
 }

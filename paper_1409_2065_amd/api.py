@@ -228,3 +228,69 @@ def components(n: int, edges, keep=None):
 
 
 __all__ = ["Problem", "build_knn_weights", "standardize_columns", "components", "CCError", "PRECISIONS"]
+
+
+class Batch:
+    """Many problems, each along its own gamma path, solved in the same
+    launches (cc_batch_create / cc_batch_run).  The problems must outlive the
+    batch; while it runs, their solver states belong to it."""
+
+    def __init__(self, problems: Sequence[Problem], gammas: Sequence[Sequence[float]],
+                 autotune: bool = True, **opts):
+        if len(problems) != len(gammas):
+            raise ValueError("one gamma path per problem")
+        self.problems = list(problems)
+        self.n_gamma = [len(g) for g in gammas]
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(g, dtype=np.float64) for g in gammas]))
+        ng = np.asarray(self.n_gamma, dtype=np.int32)
+        handles = (C.c_void_p * len(problems))(*[pr._h.value for pr in problems])
+        o = default_opts(**opts)
+        h = C.c_void_p()
+        torch.cuda.current_stream().synchronize()
+        check(_lib.load().cc_batch_create(len(problems), handles, ng.ctypes.data_as(_lib.P_i32),
+                                          flat.ctypes.data_as(_lib.P_f64), C.byref(o),
+                                          1 if autotune else 0, C.byref(h)))
+        self._h = h
+
+    def config(self) -> dict:
+        vec, gi = C.c_int32(), C.c_int32()
+        tune = (C.c_double * 3)()
+        check(_lib.load().cc_batch_config(self._h, C.byref(vec), C.byref(gi), tune))
+        return {"vec": vec.value, "graph_iters": gi.value, "tune_us": list(tune)}
+
+    def run(self, labels: bool = True):
+        """Returns (labels, infos, latency_ms): labels[b] is an (n_gamma[b], n_b)
+        int32 tensor (or None), infos[b] a list of per-gamma dicts,
+        latency_ms[b] the time from the start of the run to the end of b's path."""
+        sizes = [pr.n * g for pr, g in zip(self.problems, self.n_gamma)]
+        lab = torch.empty(max(sum(sizes), 1), dtype=torch.int32, device="cuda") if labels else None
+        total = sum(self.n_gamma)
+        infos = (_lib.SolveInfo * max(total, 1))()
+        lat = np.zeros(len(self.problems), dtype=np.float64)
+        torch.cuda.current_stream().synchronize()
+        check(_lib.load().cc_batch_run(self._h, _ptr(lab), infos, lat.ctypes.data_as(_lib.P_f64)))
+        out_lab, out_inf = [], []
+        off = g0 = 0
+        for pr, g, sz in zip(self.problems, self.n_gamma, sizes):
+            out_lab.append(lab[off:off + sz].view(g, pr.n) if labels else None)
+            out_inf.append([infos[g0 + k].as_dict() for k in range(g)])
+            off += sz
+            g0 += g
+        return out_lab, out_inf, lat
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().cc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

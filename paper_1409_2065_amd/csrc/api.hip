@@ -167,6 +167,49 @@ cc_status cc_solve_path(cc_problem_t prob, int32_t n_gamma, const double *gammas
   CC_GUARD_END
 }
 
+cc_status cc_batch_create(int32_t n_inst, const cc_problem_t *problems, const int32_t *n_gamma,
+                          const double *gammas, const cc_solve_opts *opts, int32_t autotune,
+                          cc_batch_t *out) {
+  CC_GUARD_BEGIN
+  if (!opts_ok(opts)) { set_error("opts->struct_size mismatch"); return CC_ERR_INVALID_ARG; }
+  if (n_inst < 1 || !problems) { set_error("need n_inst >= 1 problems"); return CC_ERR_INVALID_ARG; }
+  const cc_solve_opts o = resolve(opts);
+  std::vector<Problem *> probs(n_inst);
+  for (int32_t b = 0; b < n_inst; ++b) probs[b] = reinterpret_cast<Problem *>(problems[b]);
+  Batch *B = nullptr;
+  cc_status s = batch_create(n_inst, probs.data(), n_gamma, gammas, o, autotune, &B);
+  if (s != CC_OK) return s;
+  *out = reinterpret_cast<cc_batch_t>(B);
+  return CC_OK;
+  CC_GUARD_END
+}
+
+cc_status cc_batch_run(cc_batch_t batch, int32_t *labels, cc_solve_info *infos, double *latency_ms) {
+  CC_GUARD_BEGIN
+  if (!batch) { set_error("batch is NULL"); return CC_ERR_INVALID_ARG; }
+  return batch_run(reinterpret_cast<Batch *>(batch), labels, infos, latency_ms);
+  CC_GUARD_END
+}
+
+cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *graph_iters, double *tune_us) {
+  CC_GUARD_BEGIN
+  if (!batch) { set_error("batch is NULL"); return CC_ERR_INVALID_ARG; }
+  const Batch *B = reinterpret_cast<const Batch *>(batch);
+  if (vec) *vec = B->vec;
+  if (graph_iters) *graph_iters = B->graph_iters;
+  if (tune_us)
+    for (int c = 0; c < 3; ++c) tune_us[c] = c < (int)B->tune_us.size() ? B->tune_us[c] : 0.0;
+  return CC_OK;
+  CC_GUARD_END
+}
+
+cc_status cc_batch_destroy(cc_batch_t batch) {
+  CC_GUARD_BEGIN
+  batch_free(reinterpret_cast<Batch *>(batch));
+  return CC_OK;
+  CC_GUARD_END
+}
+
 cc_status cc_get_U(cc_problem_t prob, int32_t out_dtype, void *U, int64_t ldu) {
   CC_GUARD_BEGIN
   if (!prob || !U) { set_error("NULL argument"); return CC_ERR_INVALID_ARG; }

@@ -45,7 +45,23 @@ struct DevScalars {
   double dA_prev; // ||A_{m-1} - A_{m-1-K}||^2 of the last A window
   double F_cur;   // F_{m-1} once iteration m-1 has finished
   double F_last, d_last, rel_last;
-  unsigned int pad0, pad1;
+  int path_k;     // batched: index of the gamma in progress
+  int finished;   // batched: the whole gamma path is done
+};
+
+// Batched solves: what the device needs to move an instance along its gamma
+// path without the host.  Per-gamma constants are computed on the host with
+// the same arithmetic as a single solve.
+constexpr int kInfoVals = 8;  // iters, converged, status, F, d, rel, gamma, t (ticks)
+struct BatchInst {
+  int n_gamma, E;
+  DevScalars *sc0;                     // the instance's scalar slot 0
+  const double *mu, *rho, *eps, *thr;  // per gamma
+  const double *s;                     // the instance's shrink factors
+  uint8_t *fused;                      // n_gamma x E: s == 0 at the end of each gamma
+  double *info;                        // n_gamma x kInfoVals
+  unsigned long long *t_done;          // wall-clock ticks when the path finished
+  int *n_finished;                     // batch-wide count of finished paths
 };
 
 enum Prec { kF32 = CC_PREC_F32, kMixed = CC_PREC_MIXED, kF64 = CC_PREC_F64 };
@@ -88,7 +104,6 @@ struct Problem {
   int32_t *epos = nullptr;  // ELL positions of (i->j) and (j->i) per edge
   int slab_f = 0;           // > 0: LDS-slab point sweep with F-feature tiles
   bool ell_cm = false;      // ELL stored column-major (entry k of i at k*n + i)
-  double cur_rho = 1.0;     // constants of the solve in progress
   int cur_K = 64;
   double *part = nullptr;    // E x entile edge partials
   double *psum = nullptr;    // point-sweep blocks x 8 point partials
@@ -115,6 +130,42 @@ struct Problem {
   size_t prof_used = 0;                 // event sets recorded, not yet harvested
   double prof_ms[3] = {0, 0, 0};
   int64_t prof_n[3] = {0, 0, 0};
+};
+
+struct PointArgs;  // kernel argument blocks (solver.hip)
+struct EdgeArgs;
+
+// Many problems solved along their own gamma paths in the same launches.
+struct Batch {
+  std::vector<Problem *> probs;   // not owned
+  int precision = kMixed;
+  int vec = 4;                    // point-sweep features per lane (all instances)
+  int nv = 4;                     // edge-sweep features per lane (all instances)
+  int graph_iters = 32;           // MM iterations per graph replay (even)
+  cc_solve_opts opts{};
+  hipStream_t stream = nullptr;   // private: graphs are captured on it
+  std::vector<int> order;         // instances by decreasing work
+  int nblk_point = 0, nblk_edge = 0;
+  PointArgs *pargs[2] = {nullptr, nullptr};  // per instance, by scalar slot parity
+  EdgeArgs *eargs[2] = {nullptr, nullptr};
+  int2 *ptab = nullptr, *etab = nullptr;     // block -> (instance, local block)
+  BatchInst *bi = nullptr;
+  std::vector<int> n_gamma;
+  std::vector<int64_t> goff;      // first (instance, gamma) slot of each instance
+  std::vector<int64_t> foff;      // offset of each instance's fused flags
+  int64_t total_gamma = 0, total_fused = 0;
+  std::vector<double> gammas, rho, eps;
+  double *gconst = nullptr;       // mu, rho, eps, thr: 4 x total_gamma
+  uint8_t *fused = nullptr;
+  double *info = nullptr;         // total_gamma x kInfoVals
+  unsigned long long *ticks = nullptr;  // [0] start, [1 + b] path done
+  int *n_finished = nullptr;
+  int32_t *ncl = nullptr;         // clusters per (instance, gamma)
+  int32_t *fin_host = nullptr;    // pinned
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double tick_khz = 100000.0;     // wall-clock counter rate
+  std::vector<double> tune_us;    // autotuner: us per iteration for vec = 1, 2, 4
 };
 
 // ---- error reporting (thread-local message) ----
@@ -147,6 +198,12 @@ cc_status harvest_profile(Problem *P);
 cc_status components(int64_t n, int64_t E, const int32_t *ei,
                      const int32_t *ej, const uint8_t *keep, const double *s,
                      int32_t *labels, int32_t *ncl_dev, hipStream_t stream);
+
+cc_status batch_create(int32_t n_inst, Problem *const *probs, const int32_t *n_gamma,
+                       const double *gammas, const cc_solve_opts &o, int32_t autotune,
+                       Batch **out);
+cc_status batch_run(Batch *B, int32_t *labels, cc_solve_info *infos, double *latency_ms);
+void batch_free(Batch *B);
 
 // ---- weights and preparation (knn.hip) ----
 cc_status build_knn_weights(int64_t n, int64_t p, int32_t x_dtype,

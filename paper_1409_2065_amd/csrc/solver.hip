@@ -227,12 +227,19 @@ __device__ inline void block_sum_all(double (&v)[NV], double *scratch) {
   for (int q = 0; q < NV; ++q) v[q] = scratch[NW * NV + q];
 }
 
-// Logical block index: physical block b runs on XCD b % 8 (round-robin
-// dispatch); XCD x is given the x-th contiguous eighth of the logical range,
-// so each XCD sweeps a contiguous run of feature tiles.
-__device__ inline int logical_block() {
+// Block coordinates within one problem's launch: b = block index, nb =
+// blocks of the launch, lb = logical index.  Physical block b runs on XCD
+// b % 8 (round-robin dispatch); XCD x is given the x-th contiguous eighth of
+// the logical range, so each XCD sweeps a contiguous run of feature tiles.
+// A single-problem launch takes them from the hardware indices, a batched
+// launch from its block table (same mapping, so the same partial sums).
+struct Blk {
+  int b, nb, lb;
+};
+__device__ inline int xcd_remap(int b, int nb) { return (b % kXcds) * (nb / kXcds) + b / kXcds; }
+__device__ inline Blk hw_blk() {
   const int b = blockIdx.x, nb = gridDim.x;
-  return (b % kXcds) * (nb / kXcds) + b / kXcds;
+  return Blk{b, nb, xcd_remap(b, nb)};
 }
 
 // ---------------------------------------------------------------- params
@@ -247,14 +254,15 @@ struct PointArgs {
   const int32_t *degE, *colE, *eidE;
   const double *qE;     // mu w / (rho ||b||) of the previous A, per ELL entry
   const double *s;      // state shrink factors (first iteration of a solve)
-  double rho;           // constants of the solve
-  int K;
+  int K;                // stop-test window
+  int nblk;             // blocks of this problem's launch
   double *psum;         // this sweep's block partials
   const double *esum;   // partial rows of the previous edge stage
   int nrows;            // how many
   double *trace;
   const DevScalars *sin;  // scalars of the previous iteration
   DevScalars *sout;       // advanced scalars (block 0 writes)
+  const BatchInst *bi;    // batched solves only (else null)
 };
 
 // Per-edge bookkeeping shared by the fused edge kernel and the reduction
@@ -271,6 +279,7 @@ struct EdgeState {
 
 struct EdgeArgs {
   int n, ld, ntile, nitems, chunk, init, nbp;
+  int nblk;             // blocks of this problem's launch
   const void *G0, *G1;
   const int32_t *ei, *ej;
   const int32_t *itemI, *itemJ, *itemE;  // edge work items (item sweep)
@@ -333,13 +342,44 @@ __device__ inline void finish_scalars(DevScalars &h, const double (&v)[kIterSums
   h.m = m + 1;
 }
 
+// Batched solves: the gamma in progress has ended (stop rule, iteration cap
+// or a numeric error).  Block 0 records its fusion flags and info; every
+// block then moves to the next gamma with a warm start (the state stays), as
+// a single solve along a path does, or marks the path finished.
+__device__ inline void next_gamma(DevScalars &h, const BatchInst &bi, const Blk blk) {
+  const int k = h.path_k;
+  if (blk.b == 0) {
+    for (int e = threadIdx.x; e < bi.E; e += blockDim.x)
+      bi.fused[(size_t)k * bi.E + e] = bi.s[e] == 0.0 ? 1 : 0;
+    if (threadIdx.x == 0) {
+      double *inf = bi.info + (size_t)k * kInfoVals;
+      inf[0] = h.iters; inf[1] = h.converged; inf[2] = h.status;
+      inf[3] = h.F_last; inf[4] = h.d_last; inf[5] = h.rel_last; inf[6] = h.mu;
+      inf[7] = (double)wall_clock64();
+    }
+  }
+  if (k + 1 < bi.n_gamma && h.status == 0) {
+    h.mu = bi.mu[k + 1]; h.rho = bi.rho[k + 1]; h.eps = bi.eps[k + 1]; h.thr = bi.thr[k + 1];
+    h.m = 0; h.done = 0; h.converged = 0; h.status = 0; h.iters = 0;
+    h.d_prev = 0.0; h.dA_prev = 0.0; h.F_cur = 0.0;
+    h.F_last = 0.0; h.d_last = 0.0; h.rel_last = 0.0;
+    h.path_k = k + 1;
+  } else {
+    h.finished = 1;
+    if (blk.b == 0 && threadIdx.x == 0) {
+      *bi.t_done = wall_clock64();
+      atomicAdd(bi.n_finished, 1);
+    }
+  }
+}
+
 // Start of a point sweep: when a sweep is pending, sum the edge stage's
 // partial rows (column-major, the same order in every block) and finish its
 // iteration; block 0 stores the scalars of the iteration about to run (or
 // the final ones) in the other slot.  Blocks of NW waves; red:
 // (NW + 1) * kIterSums.
 template <int NW>
-__device__ inline DevScalars begin_iteration(const PointArgs &a, double *red) {
+__device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, const Blk blk) {
   double v[kIterSums];
 #pragma unroll
   for (int q = 0; q < kIterSums; ++q) v[q] = 0.0;
@@ -357,10 +397,11 @@ __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red) {
     }
   }
   DevScalars h = *a.sin;
-  const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool writer = blk.b == 0 && threadIdx.x == 0;
   if (h.pending && !h.done) {  // uniform
     block_sum_all<kIterSums, NW>(v, red);
     finish_scalars(h, v, a.trace, writer);
+    if (a.bi && h.done) next_gamma(h, *a.bi, blk);
   }
   h.pending = h.done ? 0 : 1;
   if (writer) *a.sout = h;
@@ -369,7 +410,7 @@ __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red) {
 
 // ------------------------------------------------------------- k_point
 template <int PREC, int VEC>
-__global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
+__device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   using TS = typename Traits<PREC>::TS;
   using TG = typename Traits<PREC>::TG;
   using TX = typename Traits<PREC>::TX;
@@ -379,7 +420,7 @@ __global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
   TS *U = reinterpret_cast<TS *>(a.U);
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lb = logical_block();
+  const int lb = blk.lb;
   const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
   const int W = kWave * VEC;
 
@@ -405,10 +446,10 @@ __global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
     RawIO<TX, VEC>::load(X + rowc, x0);
   }
 
-  const DevScalars hs = begin_iteration<kPointWaves>(a, red);
+  const DevScalars hs = begin_iteration<kPointWaves>(a, red, blk);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
-  const double rho = a.rho, dprev = hs.d_prev;
+  const double rho = hs.rho, dprev = hs.d_prev;
   const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
   // stop-test window: U snapshots at m = 0, K, 2K, ...; A snapshots at
   // m = K-1, 2K-1, ... (the start-of-solve A' seeds the first A window)
@@ -600,6 +641,19 @@ __global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
   }
 }
 
+template <int PREC, int VEC>
+__global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
+  point_sweep<PREC, VEC>(a, hw_blk());
+}
+
+// Batched: block q works for instance tab[q].x as its local block tab[q].y.
+template <int PREC, int VEC>
+__global__ __launch_bounds__(kPointBlock) void k_point_batch(const PointArgs *args, const int2 *tab) {
+  const int2 t = tab[blockIdx.x];
+  const PointArgs a = args[t.x];
+  point_sweep<PREC, VEC>(a, Blk{t.y, a.nblk, xcd_remap(t.y, a.nblk)});
+}
+
 // ------------------------------------------------------- k_point_slab
 // Narrow problems, where an n x F tile of the gather copy fits in LDS: one
 // block per (F-feature tile, 256 points).  The block stages the tile of A'
@@ -617,10 +671,11 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
   TG *slab = reinterpret_cast<TG *>(smem);
   __shared__ double scratch[kWavesPerBlock * kPointSums];
   __shared__ double red[(kWavesPerBlock + 1) * kIterSums];
-  const DevScalars hs = begin_iteration<kWavesPerBlock>(a, red);
+  const Blk blk = hw_blk();
+  const DevScalars hs = begin_iteration<kWavesPerBlock>(a, red, blk);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
-  const double rho = a.rho, dprev = hs.d_prev;
+  const double rho = hs.rho, dprev = hs.d_prev;
   const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
   const int K = a.K;
   const bool snapU0 = (m == 0), winU = (m > 0) && (m % K == 0);
@@ -634,7 +689,7 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
   const TX *X = reinterpret_cast<const TX *>(a.X);
   TS *U = reinterpret_cast<TS *>(a.U);
 
-  const int lb = logical_block();
+  const int lb = blk.lb;
   const int npg = (a.n + kBlock - 1) / kBlock;
   const int t = lb / npg, g = lb - t * npg;
   double ps[kPointSums] = {0, 0, 0, 0, 0, 0};
@@ -795,8 +850,8 @@ __device__ inline void edge_update(const EdgeState &es, int e, double nb2, const
   es.qE[in.p1] = q;
 }
 
-// Partial row of an edge-stage block: the point-sweep partials of rows
-// blockIdx.x, blockIdx.x + gridDim.x, ... summed in that order (pt, held by
+// Partial row of edge-stage block b of nb: the point-sweep partials of rows
+// b, b + nb, ... summed in that order (pt, held by
 // threads 0..5) and the block's edge sums, stored as one padded row for the
 // next point sweep.  The point partials of the first kGatherRows rows are
 // loaded at the start of the kernel, one value per thread, and summed at
@@ -804,14 +859,14 @@ __device__ inline void edge_update(const EdgeState &es, int e, double nb2, const
 static_assert(kEsumStride % 2 == 0 && kEsumStride > kIterSums, "partial row layout");
 constexpr int kGatherRows = 8;
 
-__device__ inline double point_partial_load(const double *psum, int nbp) {
+__device__ inline double point_partial_load(const double *psum, int nbp, const Blk blk) {
   const int k = threadIdx.x / kPointSums, q = threadIdx.x - k * kPointSums;
-  const int r = blockIdx.x + k * gridDim.x;
+  const int r = blk.b + k * blk.nb;
   return (k < kGatherRows && r < nbp) ? psum[(size_t)r * 8 + q] : 0.0;
 }
 
 // Needs blocks of at least kGatherRows * kPointSums threads; a barrier.
-__device__ inline double point_partial_sum(double mine, const double *psum, int nbp) {
+__device__ inline double point_partial_sum(double mine, const double *psum, int nbp, const Blk blk) {
   __shared__ double rows[kGatherRows * kPointSums];
   if (threadIdx.x < kGatherRows * kPointSums) rows[threadIdx.x] = mine;
   __syncthreads();
@@ -819,15 +874,16 @@ __device__ inline double point_partial_sum(double mine, const double *psum, int 
   if (threadIdx.x < kPointSums) {
 #pragma unroll
     for (int k = 0; k < kGatherRows; ++k) pt += rows[k * kPointSums + threadIdx.x];
-    for (int r = blockIdx.x + kGatherRows * gridDim.x; r < nbp; r += gridDim.x)
+    for (int r = blk.b + kGatherRows * blk.nb; r < nbp; r += blk.nb)
       pt += psum[(size_t)r * 8 + threadIdx.x];
   }
   return pt;
 }
 
-__device__ inline void edge_block_partials(double (&t3)[kEdgeSums], double pt, double *esum) {
+__device__ inline void edge_block_partials(double (&t3)[kEdgeSums], double pt, double *esum,
+                                           const Blk blk) {
   __shared__ double red[kEdgeWaves * kEdgeSums];
-  double *row = esum + (size_t)blockIdx.x * kEsumStride;
+  double *row = esum + (size_t)blk.b * kEsumStride;
   if (threadIdx.x < kPointSums) row[threadIdx.x] = pt;
   block_sum<kEdgeSums>(t3, red);
   if (threadIdx.x == 0) {
@@ -849,7 +905,8 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int q = lane / 16, l16 = lane % 16;
-  const int lb = logical_block();
+  const Blk blk = hw_blk();
+  const int lb = blk.lb;
   const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
   // An invalid quarter (past the last edge) works on the last edge and
   // stores nothing; item < nitems guarantees E >= 1.  The first item's edge
@@ -863,7 +920,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
     j0 = a.ej[ec];
   }
   if (!a.init && sc->done) return;
-  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp);
+  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp, blk);
   const int pa = sc->pa;
   // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
   const int buf = a.init ? pa : (pa ^ 1);
@@ -919,7 +976,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
     if (valid && l16 == 0) edge_update(a.es, e, acc, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
-  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp), a.esum);
+  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp, blk), a.esum, blk);
 }
 
 // Rows up to 512 wide: one wave per work item of up to kItemEdges edges
@@ -928,14 +985,14 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
 // wave), and the rows j_q in one batch; each ||a_i - a_j||^2 is a wave sum
 // and lane q finishes edge q.  Per edge one row is gathered instead of two.
 template <int PREC, int NV>
-__global__ __launch_bounds__(kEdgeBlock) void k_edge_items(EdgeArgs a) {
+__device__ __forceinline__ void edge_items_sweep(const EdgeArgs &a, const Blk blk) {
   using TG = typename Traits<PREC>::TG;
   constexpr int CH = NV < 4 ? NV : 4;  // features per load
   constexpr int NCH = NV / CH;
   const DevScalars *sc = a.sc;
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lb = logical_block();
+  const int lb = blk.lb;
   const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
   // the first item's lists are loaded before the scalars: both arrive together
   const int first = it0 + wave;
@@ -948,7 +1005,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_items(EdgeArgs a) {
     i0 = a.itemI[first];
   }
   if (!a.init && sc->done) return;
-  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp);
+  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp, blk);
   const int pa = sc->pa;
   // iteration: the new A_m sits in buffer pa^1; init: norms of buffer pa
   const int buf = a.init ? pa : (pa ^ 1);
@@ -1005,7 +1062,20 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_items(EdgeArgs a) {
     if (el >= 0) edge_update(a.es, el, mine, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
-  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp), a.esum);
+  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp, blk), a.esum, blk);
+}
+
+template <int PREC, int NV>
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_items(EdgeArgs a) {
+  edge_items_sweep<PREC, NV>(a, hw_blk());
+}
+
+// Batched: block q works for instance tab[q].x as its local block tab[q].y.
+template <int PREC, int NV>
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_items_batch(const EdgeArgs *args, const int2 *tab) {
+  const int2 t = tab[blockIdx.x];
+  const EdgeArgs a = args[t.x];
+  edge_items_sweep<PREC, NV>(a, Blk{t.y, a.nblk, xcd_remap(t.y, a.nblk)});
 }
 
 // Wide rows: one wave per (point i, 256-feature tile); each quarter-wave
@@ -1023,7 +1093,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_tiles(EdgeArgs a) {
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int q = lane / 16, l16 = lane % 16;
-  const int lb = logical_block();
+  const Blk blk = hw_blk();
+  const int lb = blk.lb;
   const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
   const int W = 64 * NPASS;
   for (int item = it0 + wave; item < it1; item += kWavesPerBlock) {
@@ -1086,7 +1157,7 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
   const int pa = sc->pa;
   const int buf = a.init ? pa : (pa ^ 1);
   const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
-  const int g = logical_block();
+  const int g = hw_blk().lb;
   const int t0 = g * tiles_per_group, t1 = min(t0 + tiles_per_group, ntiles_f);
   const int E = a.es.E;
   int ei[kEdgesPerThread], ej[kEdgesPerThread];
@@ -1141,7 +1212,8 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
 __global__ __launch_bounds__(kEdgeBlock) void k_edge_reduce(ReduceArgs a) {
   const DevScalars *sc = a.sc;
   if (!a.init && sc->done) return;
-  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp);
+  const Blk blk = hw_blk();
+  const double pmine = a.init ? 0.0 : point_partial_load(a.psum, a.nbp, blk);
   const int pa = sc->pa;
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -1156,7 +1228,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_reduce(ReduceArgs a) {
     if (lane == 0) edge_update(a.es, e, nb2, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
-  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp), a.esum);
+  edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp, blk), a.esum, blk);
 }
 
 // --------------------------------------------------------- small kernels
@@ -1168,7 +1240,7 @@ __global__ void k_set_params(DevScalars *sc, double mu, double rho, double eps,
   sc->m = 0; sc->done = 0; sc->converged = 0; sc->status = 0; sc->iters = 0;
   sc->d_prev = 0.0; sc->dA_prev = 0.0; sc->F_cur = 0.0;
   sc->F_last = 0.0; sc->d_last = 0.0; sc->rel_last = 0.0;
-  sc->pending = 0;
+  sc->pending = 0; sc->path_k = 0; sc->finished = 0;
 }
 
 __global__ void k_reset_scalars(DevScalars *sc) {
@@ -1368,8 +1440,8 @@ static hipEvent_t *prof_slot(Problem *P) {
 static PointArgs point_args(Problem *P, const Launch &Lp) {
   return PointArgs{(int)P->n, (int)P->ld, P->ntile, Lp.nitems, Lp.chunk,
                    P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
-                   P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_rho, P->cur_K,
-                   P->psum, P->esum, P->nbe, P->trace, P->sc + P->slot, P->sc + (P->slot ^ 1)};
+                   P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_K, Lp.blocks,
+                   P->psum, P->esum, P->nbe, P->trace, P->sc + P->slot, P->sc + (P->slot ^ 1), nullptr};
 }
 
 template <int PREC, int VEC>
@@ -1383,7 +1455,7 @@ static EdgeState edge_state(Problem *P) {
 }
 
 static EdgeArgs edge_args(Problem *P, const Launch &Le, int init, int nbp) {
-  return EdgeArgs{(int)P->n, (int)P->ld, P->entile, Le.nitems, Le.chunk, init, nbp,
+  return EdgeArgs{(int)P->n, (int)P->ld, P->entile, Le.nitems, Le.chunk, init, nbp, Le.blocks,
                   P->G[0], P->G[1], P->ei, P->ej, P->itemI, P->itemJ, P->itemE,
                   P->rowptr, P->uptr, P->col, P->eid, P->part,
                   edge_state(P), P->esum, P->psum, P->sc + P->slot};
@@ -1948,6 +2020,19 @@ static cc_status read_scalars(Problem *P) {
   return CC_OK;
 }
 
+// rho, eps and the stop threshold tol * eta of a solve at gamma (eta the
+// effective sqrt(eps) / rho when eps is given).
+static void solve_constants(const Problem *P, double gamma, const cc_solve_opts &o, double *rho,
+                            double *eps, double *thr) {
+  double r = o.rho > 0 ? o.rho : 2.0 * std::sqrt(P->dev2 + gamma * gamma * P->w2);
+  if (!(r > 0.0)) r = 1.0;
+  const double e = o.eps > 0 ? o.eps : (o.eta * r) * (o.eta * r);
+  const double eta = std::sqrt(e) / r;
+  *rho = r;
+  *eps = e;
+  *thr = o.tol > 0 ? o.tol * eta : 0.0;
+}
+
 cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info *info) {
   if (!(gamma >= 0.0) || !std::isfinite(gamma)) { set_error("gamma must be finite and >= 0"); return CC_ERR_INVALID_ARG; }
   if (o.max_iter < 1) { set_error("max_iter must be >= 1"); return CC_ERR_INVALID_ARG; }
@@ -1956,12 +2041,8 @@ cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info 
   if (!(o.eta > 0.0) && !(o.eps > 0.0)) { set_error("need eta > 0 or eps > 0"); return CC_ERR_INVALID_ARG; }
   const auto t0 = std::chrono::steady_clock::now();
   if (!o.warm_start || !P->state_valid) CC_TRY(reset_state(P));
-  double rho = o.rho > 0 ? o.rho : 2.0 * std::sqrt(P->dev2 + gamma * gamma * P->w2);
-  if (!(rho > 0.0)) rho = 1.0;
-  const double eps = o.eps > 0 ? o.eps : (o.eta * rho) * (o.eta * rho);
-  const double eta = std::sqrt(eps) / rho;
-  const double thr = o.tol > 0 ? o.tol * eta : 0.0;
-  P->cur_rho = rho;
+  double rho, eps, thr;
+  solve_constants(P, gamma, o, &rho, &eps, &thr);
   P->cur_K = o.test_every;
   if (o.record_objective) {
     const int64_t need = (int64_t)o.max_iter + 2;
@@ -2107,6 +2188,374 @@ cc_status get_state(Problem *P, double *U, double *A, int64_t ld, double *s) {
   if (P->E > 0) CC_HIP(hipMemcpyAsync(s, P->s, P->E * 8, hipMemcpyDeviceToDevice, P->stream));
   CC_HIP(hipGetLastError());
   return CC_OK;
+}
+
+
+// ============================================================ batched solves
+// Instances advance together: per MM iteration one point-sweep launch and
+// one edge-sweep launch cover every instance (a block table maps each block
+// to an instance and its local block); each instance keeps its own scalars,
+// partial rows and stop rule and moves along its own gamma path on the
+// device.  Graph replays of graph_iters iterations run until every path is
+// done.
+
+// Slot 0 of every instance: the first gamma of its path (the state and its
+// buffer index pa stay, as for a warm-started solve).
+__global__ void k_batch_init(int n_inst, const BatchInst *bi, int max_iter, int K,
+                             unsigned long long *ticks, int *n_finished) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) {
+    ticks[0] = wall_clock64();
+    *n_finished = 0;
+  }
+  if (b >= n_inst) return;
+  DevScalars *sc = bi[b].sc0;
+  sc->mu = bi[b].mu[0]; sc->rho = bi[b].rho[0]; sc->eps = bi[b].eps[0]; sc->thr = bi[b].thr[0];
+  sc->max_iter = max_iter; sc->record = 0; sc->K = K;
+  sc->m = 0; sc->done = 0; sc->converged = 0; sc->status = 0; sc->iters = 0;
+  sc->d_prev = 0.0; sc->dA_prev = 0.0; sc->F_cur = 0.0;
+  sc->F_last = 0.0; sc->d_last = 0.0; sc->rel_last = 0.0;
+  sc->pending = 0; sc->path_k = 0; sc->finished = 0;
+}
+
+__global__ void k_batch_done_ticks(int n_inst, const BatchInst *bi, unsigned long long *out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n_inst) out[b] = *bi[b].t_done;
+}
+
+template <int PREC>
+static void launch_batch_point_p(Batch *B, int par) {
+  const dim3 g(B->nblk_point), t(kPointBlock);
+  switch (B->vec) {
+    case 1: hipLaunchKernelGGL((k_point_batch<PREC, 1>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
+    case 2: hipLaunchKernelGGL((k_point_batch<PREC, 2>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
+    default: hipLaunchKernelGGL((k_point_batch<PREC, 4>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
+  }
+}
+
+template <int PREC>
+static void launch_batch_edge_p(Batch *B, int par) {
+  const dim3 g(B->nblk_edge), t(kEdgeBlock);
+  switch (B->nv) {
+    case 1: hipLaunchKernelGGL((k_edge_items_batch<PREC, 1>), g, t, 0, B->stream, B->eargs[par], B->etab); break;
+    case 2: hipLaunchKernelGGL((k_edge_items_batch<PREC, 2>), g, t, 0, B->stream, B->eargs[par], B->etab); break;
+    case 4: hipLaunchKernelGGL((k_edge_items_batch<PREC, 4>), g, t, 0, B->stream, B->eargs[par], B->etab); break;
+    default:
+      if constexpr (PREC != kF64)
+        hipLaunchKernelGGL((k_edge_items_batch<PREC, 8>), g, t, 0, B->stream, B->eargs[par], B->etab);
+      break;
+  }
+}
+
+static void launch_batch_iteration(Batch *B, int par) {
+  if (B->precision == kF32) { launch_batch_point_p<kF32>(B, par); launch_batch_edge_p<kF32>(B, par); }
+  else if (B->precision == kF64) { launch_batch_point_p<kF64>(B, par); launch_batch_edge_p<kF64>(B, par); }
+  else { launch_batch_point_p<kMixed>(B, par); launch_batch_edge_p<kMixed>(B, par); }
+}
+
+template <typename T>
+static cc_status upload(T **dst, const std::vector<T> &v, hipStream_t st) {
+  if (*dst) (void)hipFree(*dst);
+  *dst = nullptr;
+  CC_TRY(dmalloc((void **)dst, std::max<size_t>(v.size(), 1) * sizeof(T)));
+  if (!v.empty()) CC_HIP(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return CC_OK;
+}
+
+// Tile shape vec for every instance: block tables, per-instance arguments for
+// both scalar-slot parities, and the graph of graph_iters iterations.
+static cc_status batch_configure(Batch *B, int vec) {
+  B->vec = vec;
+  B->nv = 1;
+  const int n_inst = (int)B->probs.size();
+  std::vector<PointArgs> pa[2];
+  std::vector<EdgeArgs> ea[2];
+  std::vector<int> pblocks(n_inst), eblocks(n_inst);
+  for (int b = 0; b < n_inst; ++b) {
+    Problem *P = B->probs[b];
+    P->vec = vec;
+    P->tile_w = kWave * vec;
+    P->ntile = (int)cdiv(P->ld, P->tile_w);
+    P->cur_K = B->opts.test_every;
+    B->nv = std::max(B->nv, P->item_nv);
+    const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves);
+    const Launch Li = edge_items_grid(P->n_items);
+    pblocks[b] = Lp.blocks;
+    eblocks[b] = Li.blocks;
+    for (int par = 0; par < 2; ++par) {
+      P->slot = par;
+      PointArgs x = point_args(P, Lp);
+      x.bi = B->bi + b;
+      pa[par].push_back(x);
+      P->slot = par ^ 1;
+      ea[par].push_back(edge_args(P, Li, 0, Lp.blocks));
+    }
+    P->slot = 0;
+  }
+  std::vector<int2> pt, et;
+  for (int b : B->order) {
+    for (int q = 0; q < pblocks[b]; ++q) pt.push_back(make_int2(b, q));
+    for (int q = 0; q < eblocks[b]; ++q) et.push_back(make_int2(b, q));
+  }
+  B->nblk_point = (int)pt.size();
+  B->nblk_edge = (int)et.size();
+  for (int par = 0; par < 2; ++par) {
+    CC_TRY(upload(&B->pargs[par], pa[par], B->stream));
+    CC_TRY(upload(&B->eargs[par], ea[par], B->stream));
+  }
+  CC_TRY(upload(&B->ptab, pt, B->stream));
+  CC_TRY(upload(&B->etab, et, B->stream));
+  CC_HIP(hipStreamSynchronize(B->stream));
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->gexec = nullptr;
+  B->graph = nullptr;
+  CC_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+  for (int it = 0; it < B->graph_iters; ++it) launch_batch_iteration(B, it & 1);
+  CC_HIP(hipStreamEndCapture(B->stream, &B->graph));
+  CC_HIP(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+  return CC_OK;
+}
+
+// Every instance to scalar slot 0 with the first gamma of its path.
+static cc_status batch_start(Batch *B) {
+  for (Problem *P : B->probs) {
+    CC_HIP(hipStreamSynchronize(P->stream));
+    if (P->slot != 0) {
+      CC_HIP(hipMemcpyAsync(P->sc, P->sc + 1, sizeof(DevScalars), hipMemcpyDeviceToDevice, B->stream));
+      P->slot = 0;
+    }
+  }
+  const int n_inst = (int)B->probs.size();
+  hipLaunchKernelGGL(k_batch_init, dim3((int)cdiv(n_inst, 256)), dim3(256), 0, B->stream, n_inst,
+                     (const BatchInst *)B->bi, B->opts.max_iter, B->opts.test_every, B->ticks,
+                     B->n_finished);
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+static cc_status check_opts(const cc_solve_opts &o) {
+  if (o.max_iter < 1) { set_error("max_iter must be >= 1"); return CC_ERR_INVALID_ARG; }
+  if (o.test_every < 1) { set_error("test_every must be >= 1"); return CC_ERR_INVALID_ARG; }
+  if (!(o.tol >= 0.0)) { set_error("tol must be >= 0"); return CC_ERR_INVALID_ARG; }
+  if (!(o.eta > 0.0) && !(o.eps > 0.0)) { set_error("need eta > 0 or eps > 0"); return CC_ERR_INVALID_ARG; }
+  return CC_OK;
+}
+
+void batch_free(Batch *B) {
+  if (!B) return;
+  if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  void *bufs[] = {B->pargs[0], B->pargs[1], B->eargs[0], B->eargs[1], B->ptab, B->etab, B->bi,
+                  B->gconst, B->fused, B->info, B->ticks, B->n_finished, B->ncl};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (B->fin_host) (void)hipHostFree(B->fin_host);
+  if (B->stream) (void)hipStreamDestroy(B->stream);
+  delete B;
+}
+
+// Runs the batch from the instances' current states; returns us per MM
+// iteration over `iters` iterations (graph replays).
+static cc_status batch_time(Batch *B, int replays, double *us) {
+  CC_TRY(batch_start(B));
+  hipEvent_t e0, e1;
+  CC_HIP(hipEventCreate(&e0));
+  CC_HIP(hipEventCreate(&e1));
+  CC_HIP(hipGraphLaunch(B->gexec, B->stream));  // warm-up
+  CC_HIP(hipEventRecord(e0, B->stream));
+  for (int r = 0; r < replays; ++r) CC_HIP(hipGraphLaunch(B->gexec, B->stream));
+  CC_HIP(hipEventRecord(e1, B->stream));
+  CC_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  CC_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = 1e3 * ms / ((double)replays * B->graph_iters);
+  return CC_OK;
+}
+
+cc_status batch_create(int32_t n_inst, Problem *const *probs, const int32_t *n_gamma,
+                       const double *gammas, const cc_solve_opts &o, int32_t autotune,
+                       Batch **out) {
+  if (!out) { set_error("out is NULL"); return CC_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (n_inst < 1 || !probs || !n_gamma || !gammas) { set_error("need n_inst >= 1 and non-NULL arrays"); return CC_ERR_INVALID_ARG; }
+  CC_TRY(check_opts(o));
+  int64_t total = 0;
+  for (int b = 0; b < n_inst; ++b) {
+    const Problem *P = probs[b];
+    if (!P) { set_error("problem " + std::to_string(b) + " is NULL"); return CC_ERR_INVALID_ARG; }
+    if (P->precision != probs[0]->precision) { set_error("all problems of a batch need the same precision"); return CC_ERR_INVALID_ARG; }
+    if (!P->eitems || P->slab_f > 0) {
+      set_error("problem " + std::to_string(b) + ": rows wider than a batched sweep takes (p <= 512, 256 in FP64)");
+      return CC_ERR_INVALID_ARG;
+    }
+    if (n_gamma[b] < 1) { set_error("every instance needs at least one gamma"); return CC_ERR_INVALID_ARG; }
+    for (int b2 = 0; b2 < b; ++b2)
+      if (probs[b2] == P) { set_error("a problem appears twice in the batch"); return CC_ERR_INVALID_ARG; }
+    total += n_gamma[b];
+  }
+  for (int64_t k = 0; k < total; ++k)
+    if (!(gammas[k] >= 0.0) || !std::isfinite(gammas[k])) { set_error("gammas must be finite and >= 0"); return CC_ERR_INVALID_ARG; }
+
+  Batch *B = new (std::nothrow) Batch();
+  if (!B) { set_error("host allocation failed"); return CC_ERR_OUT_OF_MEMORY; }
+  struct Guard { Batch *&B; bool ok = false; ~Guard() { if (!ok) batch_free(B); } } guard{B};
+  B->probs.assign(probs, probs + n_inst);
+  B->precision = probs[0]->precision;
+  B->opts = o;
+  B->n_gamma.assign(n_gamma, n_gamma + n_inst);
+  B->total_gamma = total;
+  CC_HIP(hipStreamCreate(&B->stream));
+  int dev = 0, khz = 0;
+  CC_HIP(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+    B->tick_khz = khz;
+
+  // per-(instance, gamma) constants, computed as a single solve does
+  std::vector<double> hmu(total), hrho(total), heps(total), hthr(total);
+  B->goff.resize(n_inst);
+  B->foff.resize(n_inst);
+  int64_t g = 0, f = 0;
+  for (int b = 0; b < n_inst; ++b) {
+    B->goff[b] = g;
+    B->foff[b] = f;
+    for (int k = 0; k < n_gamma[b]; ++k, ++g) {
+      hmu[g] = gammas[g];
+      solve_constants(probs[b], gammas[g], o, &hrho[g], &heps[g], &hthr[g]);
+    }
+    f += (int64_t)n_gamma[b] * probs[b]->E;
+  }
+  B->total_fused = f;
+  B->gammas = hmu;
+  B->rho = hrho;
+  B->eps = heps;
+  std::vector<double> gc;
+  gc.insert(gc.end(), hmu.begin(), hmu.end());
+  gc.insert(gc.end(), hrho.begin(), hrho.end());
+  gc.insert(gc.end(), heps.begin(), heps.end());
+  gc.insert(gc.end(), hthr.begin(), hthr.end());
+  CC_TRY(upload(&B->gconst, gc, B->stream));
+  CC_TRY(dmalloc((void **)&B->fused, std::max<int64_t>(f, 1)));
+  CC_TRY(dmalloc((void **)&B->info, total * kInfoVals * 8));
+  CC_TRY(dmalloc((void **)&B->ticks, (1 + 2 * (size_t)n_inst) * 8));
+  CC_TRY(dmalloc((void **)&B->n_finished, 4));
+  CC_TRY(dmalloc((void **)&B->ncl, total * 4));
+  CC_HIP(hipHostMalloc((void **)&B->fin_host, 64, hipHostMallocDefault));
+  std::vector<BatchInst> bis(n_inst);
+  for (int b = 0; b < n_inst; ++b) {
+    const int64_t g0 = B->goff[b];
+    Problem *P = probs[b];
+    bis[b] = BatchInst{n_gamma[b], (int)P->E, P->sc, B->gconst + g0, B->gconst + total + g0,
+                       B->gconst + 2 * total + g0, B->gconst + 3 * total + g0, P->s,
+                       B->fused + B->foff[b], B->info + g0 * kInfoVals, B->ticks + 1 + n_inst + b,
+                       B->n_finished};
+  }
+  CC_TRY(upload(&B->bi, bis, B->stream));
+  // bigger instances first in the block tables
+  B->order.resize(n_inst);
+  std::iota(B->order.begin(), B->order.end(), 0);
+  std::stable_sort(B->order.begin(), B->order.end(), [&](int a, int b) {
+    return probs[a]->n * probs[a]->ld + 2 * probs[a]->E * probs[a]->ld >
+           probs[b]->n * probs[b]->ld + 2 * probs[b]->E * probs[b]->ld;
+  });
+
+  if (autotune) {
+    // point-sweep tile widths 64, 128 and 256 features: time a few graph
+    // replays of each from the instances' initial states
+    double best = 1e300;
+    int best_vec = 4;
+    B->tune_us.assign(3, 0.0);
+    const int vecs[3] = {1, 2, 4};
+    for (int c = 0; c < 3; ++c) {
+      for (Problem *P : B->probs) CC_TRY(reset_state(P));
+      CC_TRY(batch_configure(B, vecs[c]));
+      double us = 0.0;
+      CC_TRY(batch_time(B, 2, &us));
+      B->tune_us[c] = us;
+      if (us < best) { best = us; best_vec = vecs[c]; }
+    }
+    for (Problem *P : B->probs) CC_TRY(reset_state(P));
+    CC_TRY(batch_configure(B, best_vec));
+  } else {
+    int64_t maxld = 0;
+    for (Problem *P : B->probs) maxld = std::max<int64_t>(maxld, P->ld);
+    CC_TRY(batch_configure(B, maxld > 128 ? 4 : (maxld > 64 ? 2 : 1)));
+  }
+  guard.ok = true;
+  *out = B;
+  return CC_OK;
+}
+
+cc_status batch_run(Batch *B, int32_t *labels, cc_solve_info *infos, double *latency_ms) {
+  const int n_inst = (int)B->probs.size();
+  CC_TRY(batch_start(B));
+  // every path ends by its iteration caps: sum over its gammas of max_iter + 2
+  int64_t budget = 0;
+  for (int b = 0; b < n_inst; ++b)
+    budget = std::max<int64_t>(budget, (int64_t)B->n_gamma[b] * ((int64_t)B->opts.max_iter + 2));
+  const int64_t max_replays = cdiv(budget, B->graph_iters) + 2;
+  bool finished = false;
+  for (int64_t r = 0; r < max_replays; ++r) {
+    CC_HIP(hipGraphLaunch(B->gexec, B->stream));
+    CC_HIP(hipMemcpyAsync(B->fin_host, B->n_finished, 4, hipMemcpyDeviceToHost, B->stream));
+    CC_HIP(hipStreamSynchronize(B->stream));
+    if (B->fin_host[0] >= n_inst) { finished = true; break; }
+  }
+  if (!finished) { set_error("batch did not finish within its iteration caps"); return CC_ERR_STATE; }
+  // graph_iters is even: every instance is back on scalar slot 0
+  std::vector<double> hinfo(B->total_gamma * kInfoVals);
+  CC_HIP(hipMemcpyAsync(hinfo.data(), B->info, hinfo.size() * 8, hipMemcpyDeviceToHost, B->stream));
+  std::vector<unsigned long long> ticks(1 + 2 * (size_t)n_inst);
+  hipLaunchKernelGGL(k_batch_done_ticks, dim3((int)cdiv(n_inst, 256)), dim3(256), 0, B->stream, n_inst,
+                     (const BatchInst *)B->bi, B->ticks + 1);
+  CC_HIP(hipMemcpyAsync(ticks.data(), B->ticks, ticks.size() * 8, hipMemcpyDeviceToHost, B->stream));
+  // labels of every (instance, gamma) from its recorded fusion flags
+  int64_t loff = 0;
+  for (int b = 0; b < n_inst; ++b) {
+    Problem *P = B->probs[b];
+    for (int k = 0; k < B->n_gamma[b]; ++k) {
+      const int64_t gk = B->goff[b] + k;
+      if (labels)
+        CC_TRY(components(P->n, P->E, P->ei, P->ej, B->fused + B->foff[b] + (int64_t)k * P->E, nullptr,
+                          labels + loff, B->ncl + gk, B->stream));
+      loff += P->n;
+    }
+  }
+  std::vector<int32_t> hncl(B->total_gamma, 0);
+  if (labels) CC_HIP(hipMemcpyAsync(hncl.data(), B->ncl, hncl.size() * 4, hipMemcpyDeviceToHost, B->stream));
+  CC_HIP(hipStreamSynchronize(B->stream));
+  cc_status st = CC_OK;
+  for (int b = 0; b < n_inst; ++b) {
+    Problem *P = B->probs[b];
+    for (int k = 0; k < B->n_gamma[b]; ++k) {
+      const int64_t gk = B->goff[b] + k;
+      const double *v = &hinfo[gk * kInfoVals];
+      const int status = (int)v[2];
+      if (status != 0) {
+        st = (cc_status)status;
+        set_error("instance " + std::to_string(b) + ": d or the objective became non-finite");
+        P->state_valid = false;
+      }
+      if (infos) {
+        cc_solve_info &in = infos[gk];
+        in.iters = (int32_t)v[0];
+        in.converged = (int32_t)v[1];
+        in.n_clusters = hncl[gk];
+        in.status = status;
+        in.gamma = B->gammas[gk];
+        in.objective = v[3];
+        in.d = v[4];
+        in.rel_change = v[5];
+        in.rho = B->rho[gk];
+        in.eps = B->eps[gk];
+        in.seconds = (v[7] - (double)ticks[0]) / (B->tick_khz * 1e3);
+      }
+    }
+    if (latency_ms) latency_ms[b] = (double)(ticks[1 + b] - ticks[0]) / B->tick_khz;
+  }
+  return st;
 }
 
 }  // namespace ccmi
