@@ -296,8 +296,10 @@ cc_status cc_components(int64_t n, int64_t n_edges, const int32_t *ei,
  * finite and >= 0).  opts may be NULL (defaults); each gamma is solved as
  * cc_solve would with these options, warm-started from the previous one
  * (the first from the problem's current state).  autotune != 0 times a few
- * iterations of each point-sweep tile width (64, 128, 256 features) and
- * keeps the fastest; it leaves every problem at its initial state.  The
+ * iterations of each point-sweep tile width (64, 128, 256 features) with
+ * about 1, 4 and 16 work items per wave (a wave with several prefetches the
+ * next), and keeps the fastest; it leaves every problem at its initial
+ * state.  The
  * batch refers to the problems (it does not own them): destroy the batch
  * first.  A problem's solver state belongs to the batch while it runs.
  *
@@ -312,18 +314,20 @@ cc_status cc_components(int64_t n, int64_t n_edges, const int32_t *ei,
  * Returns CC_ERR_NUMERIC if any instance's d or objective became
  * non-finite (its path stops there; the others finish).
  *
- * cc_batch_config: the chosen point-sweep features per lane (vec: tile
- * width 64 * vec), the MM iterations per graph replay, and (tune_us, host,
- * 3 entries, may be NULL) the autotuner's microseconds per iteration for
- * vec = 1, 2, 4 (zeros without autotuning). */
+ * cc_batch_config (host outputs, any may be NULL): the chosen point-sweep
+ * features per lane (vec: tile width 64 * vec), work items per wave, the MM
+ * iterations per graph replay, and tune_us (9 entries): the autotuner's
+ * microseconds per iteration for (vec, items per wave) = (1,1), (1,4),
+ * (1,16), (2,1), (2,4), (2,16), (4,1), (4,4), (4,16) (zeros without
+ * autotuning). */
 cc_status cc_batch_create(int32_t n_inst, const cc_problem_t *problems,
                           const int32_t *n_gamma, const double *gammas,
                           const cc_solve_opts *opts, int32_t autotune,
                           cc_batch_t *out);
 cc_status cc_batch_run(cc_batch_t batch, int32_t *labels, cc_solve_info *infos,
                        double *latency_ms);
-cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *graph_iters,
-                          double *tune_us);
+cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *items_per_wave,
+                          int32_t *graph_iters, double *tune_us);
 cc_status cc_batch_destroy(cc_batch_t batch);
 
 #ifdef __cplusplus

@@ -82,7 +82,7 @@ SIGNATURES = {
     "cc_components": (i32, [i64, i64, vp, vp, vp, vp, P_i32, vp]),
     "cc_batch_create": (i32, [i32, C.POINTER(vp), P_i32, P_f64, C.POINTER(SolveOpts), i32, C.POINTER(vp)]),
     "cc_batch_run": (i32, [vp, vp, C.POINTER(SolveInfo), P_f64]),
-    "cc_batch_config": (i32, [vp, P_i32, P_i32, P_f64]),
+    "cc_batch_config": (i32, [vp, P_i32, P_i32, P_i32, P_f64]),
     "cc_batch_destroy": (i32, [vp]),
 }
 

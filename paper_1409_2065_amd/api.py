@@ -253,10 +253,10 @@ class Batch:
         self._h = h
 
     def config(self) -> dict:
-        vec, gi = C.c_int32(), C.c_int32()
-        tune = (C.c_double * 3)()
-        check(_lib.load().cc_batch_config(self._h, C.byref(vec), C.byref(gi), tune))
-        return {"vec": vec.value, "graph_iters": gi.value, "tune_us": list(tune)}
+        vec, ipw, gi = C.c_int32(), C.c_int32(), C.c_int32()
+        tune = (C.c_double * 9)()
+        check(_lib.load().cc_batch_config(self._h, C.byref(vec), C.byref(ipw), C.byref(gi), tune))
+        return {"vec": vec.value, "items_per_wave": ipw.value, "graph_iters": gi.value, "tune_us": list(tune)}
 
     def run(self, labels: bool = True):
         """Returns (labels, infos, latency_ms): labels[b] is an (n_gamma[b], n_b)

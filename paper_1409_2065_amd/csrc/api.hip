@@ -191,14 +191,16 @@ cc_status cc_batch_run(cc_batch_t batch, int32_t *labels, cc_solve_info *infos, 
   CC_GUARD_END
 }
 
-cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *graph_iters, double *tune_us) {
+cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *items_per_wave,
+                          int32_t *graph_iters, double *tune_us) {
   CC_GUARD_BEGIN
   if (!batch) { set_error("batch is NULL"); return CC_ERR_INVALID_ARG; }
   const Batch *B = reinterpret_cast<const Batch *>(batch);
   if (vec) *vec = B->vec;
+  if (items_per_wave) *items_per_wave = B->ipw;
   if (graph_iters) *graph_iters = B->graph_iters;
   if (tune_us)
-    for (int c = 0; c < 3; ++c) tune_us[c] = c < (int)B->tune_us.size() ? B->tune_us[c] : 0.0;
+    for (int c = 0; c < 9; ++c) tune_us[c] = c < (int)B->tune_us.size() ? B->tune_us[c] : 0.0;
   return CC_OK;
   CC_GUARD_END
 }

@@ -73,6 +73,7 @@ struct Problem {
   int ntile = 1;      // point-sweep feature tiles of width tile_w
   int tile_w = 256;   // features per tile (64 lanes x vec)
   int vec = 4;
+  int ipw = 1;        // about this many items per wave in the point and item edge sweeps
   int entile = 1;     // edge-sweep tiles (1: the fused edge kernel)
   int npass = 4;      // 64-feature passes per edge tile
   bool efused = true;
@@ -140,6 +141,8 @@ struct Batch {
   std::vector<Problem *> probs;   // not owned
   int precision = kMixed;
   int vec = 4;                    // point-sweep features per lane (all instances)
+  int ipw = 1;                    // items per wave in both sweeps
+  bool prefetch = false;          // point sweep prefetches each next item (ipw > 1)
   int nv = 4;                     // edge-sweep features per lane (all instances)
   int graph_iters = 32;           // MM iterations per graph replay (even)
   cc_solve_opts opts{};

@@ -179,6 +179,45 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Sums over the wave of 8 values per lane, value q's total returned to lane
+// q (lanes 8..63 get some total).  Transpose steps halve the values held per
+// lane (pairs of lanes 32, 16, 8 apart swap halves), leaving value
+// 4 b5 + 2 b4 + b3 (b = lane bits) summed over 8 lanes; the 8-lane groups
+// then reduce, and lane q reads the total of value q from lane 8q.  A fixed
+// order: every run gives the same bits.
+__device__ inline double wave_sum8(double (&v)[8]) {
+  const int lane = threadIdx.x % kWave;
+  {
+    const bool hi = (lane & 32) != 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double send = hi ? v[j] : v[4 + j];
+      const double keep = hi ? v[4 + j] : v[j];
+      v[j] = keep + __shfl_xor(send, 32, kWave);
+    }
+  }
+  {
+    const bool hi = (lane & 16) != 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double send = hi ? v[j] : v[2 + j];
+      const double keep = hi ? v[2 + j] : v[j];
+      v[j] = keep + __shfl_xor(send, 16, kWave);
+    }
+  }
+  double t;
+  {
+    const bool hi = (lane & 8) != 0;
+    const double send = hi ? v[0] : v[1];
+    const double keep = hi ? v[1] : v[0];
+    t = keep + __shfl_xor(send, 8, kWave);
+  }
+  t += __shfl_xor(t, 4, kWave);
+  t += __shfl_xor(t, 2, kWave);
+  t += __shfl_xor(t, 1, kWave);
+  return __shfl(t, (8 * lane) % kWave, kWave);
+}
+
 // Fixed-order block reduction of NV doubles per thread; result valid in
 // thread 0.  Uses a shared scratch of (waves per block) * NV doubles.
 template <int NV>
@@ -236,7 +275,9 @@ __device__ inline void block_sum_all(double (&v)[NV], double *scratch) {
 struct Blk {
   int b, nb, lb;
 };
-__device__ inline int xcd_remap(int b, int nb) { return (b % kXcds) * (nb / kXcds) + b / kXcds; }
+__device__ inline int xcd_remap(int b, int nb) {
+  return nb % kXcds == 0 ? (b % kXcds) * (nb / kXcds) + b / kXcds : b;  // small grids: identity
+}
 __device__ inline Blk hw_blk() {
   const int b = blockIdx.x, nb = gridDim.x;
   return Blk{b, nb, xcd_remap(b, nb)};
@@ -378,7 +419,7 @@ __device__ inline void next_gamma(DevScalars &h, const BatchInst &bi, const Blk 
 // iteration; block 0 stores the scalars of the iteration about to run (or
 // the final ones) in the other slot.  Blocks of NW waves; red:
 // (NW + 1) * kIterSums.
-template <int NW>
+template <int NW, bool BATCH = false>
 __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, const Blk blk) {
   double v[kIterSums];
 #pragma unroll
@@ -401,7 +442,9 @@ __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, co
   if (h.pending && !h.done) {  // uniform
     block_sum_all<kIterSums, NW>(v, red);
     finish_scalars(h, v, a.trace, writer);
-    if (a.bi && h.done) next_gamma(h, *a.bi, blk);
+    if constexpr (BATCH) {
+      if (h.done) next_gamma(h, *a.bi, blk);
+    }
   }
   h.pending = h.done ? 0 : 1;
   if (writer) *a.sout = h;
@@ -409,7 +452,7 @@ __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, co
 }
 
 // ------------------------------------------------------------- k_point
-template <int PREC, int VEC>
+template <int PREC, int VEC, bool PF, bool BATCH>
 __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   using TS = typename Traits<PREC>::TS;
   using TG = typename Traits<PREC>::TG;
@@ -427,26 +470,32 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   // The first item's loads that do not depend on the scalars (mask, the
   // neighbour slots and their q, the U and X rows) are issued before the
   // previous iteration is finished, so they overlap that reduction.
+  // With PF, every item's such loads are issued while the previous item
+  // gathers (a wave with several items then waits on one chain per item).
   const int first = it0 + wave;
   uint32_t mr0 = 0xffffffffu;
   int jl0 = -1;
   double ql0 = 0.0;
   TS up0[VEC];
   TX x0[VEC];
-  if (first < it1) {
-    const int t = first / a.n, i = first - t * a.n;
+  auto preload = [&](int item) {
+    const int t = item / a.n, i = item - t * a.n;
     const int f0 = t * W + lane * VEC;
     const size_t rowc = (size_t)i * a.ld + (f0 < a.ld ? f0 : 0);
+    mr0 = 0xffffffffu;
     if (a.M) mr0 = RawMask<VEC>::load(a.M + rowc);
+    jl0 = -1;
+    ql0 = 0.0;
     if (lane < a.ell_s) {
       jl0 = a.colE[i * a.ell_s + lane];
       ql0 = a.qE[i * a.ell_s + lane];  // unused in the first iteration of a solve
     }
     RawIO<TS, VEC>::load(U + rowc, up0);
     RawIO<TX, VEC>::load(X + rowc, x0);
-  }
+  };
+  if (first < it1) preload(first);
 
-  const DevScalars hs = begin_iteration<kPointWaves>(a, red, blk);
+  const DevScalars hs = begin_iteration<kPointWaves, BATCH>(a, red, blk);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
   const double rho = hs.rho, dprev = hs.d_prev;
@@ -484,7 +533,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     TX xr[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) { upr[v] = up0[v]; xr[v] = x0[v]; }
-    if (item != first) {
+    if (!PF && item != first) {
       if (a.M) mr = RawMask<VEC>::load(a.M + rowc);
       jl = -1;
       ql = 0.0;
@@ -499,6 +548,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     TS apr[VEC];
     RawIO<TG, VEC>::load(Gp + rowc, gr);
     RawIO<TS, VEC>::load(Ap + rowc, apr);
+    if (PF && item + kPointWaves < it1) preload(item + kPointWaves);
     double sumg[VEC], sumcg[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) sumg[v] = sumcg[v] = 0.0;
@@ -641,17 +691,18 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   }
 }
 
-template <int PREC, int VEC>
+// PF: prefetch each next item (for waves with several items).
+template <int PREC, int VEC, bool PF>
 __global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
-  point_sweep<PREC, VEC>(a, hw_blk());
+  point_sweep<PREC, VEC, PF, false>(a, hw_blk());
 }
 
 // Batched: block q works for instance tab[q].x as its local block tab[q].y.
-template <int PREC, int VEC>
+template <int PREC, int VEC, bool PF>
 __global__ __launch_bounds__(kPointBlock) void k_point_batch(const PointArgs *args, const int2 *tab) {
   const int2 t = tab[blockIdx.x];
   const PointArgs a = args[t.x];
-  point_sweep<PREC, VEC>(a, Blk{t.y, a.nblk, xcd_remap(t.y, a.nblk)});
+  point_sweep<PREC, VEC, PF, true>(a, Blk{t.y, a.nblk, xcd_remap(t.y, a.nblk)});
 }
 
 // ------------------------------------------------------- k_point_slab
@@ -1012,17 +1063,19 @@ __device__ __forceinline__ void edge_items_sweep(const EdgeArgs &a, const Blk bl
   const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
   double t3[kEdgeSums] = {0.0, 0.0, 0.0};
   for (int item = first; item < it1; item += kEdgeWaves) {
-    int jl = jl0, el = el0, i = i0;
-    if (item != first) {
-      jl = -1;
-      el = -1;
+    int jl = jl0, el = el0;
+    const int i = __builtin_amdgcn_readfirstlane(i0);
+    // the next item's lists load while this one gathers
+    const int nxt = item + kEdgeWaves;
+    if (nxt < it1) {
+      jl0 = -1;
+      el0 = -1;
       if (lane < kItemEdges) {
-        jl = a.itemJ[(size_t)item * kItemEdges + lane];
-        el = a.itemE[(size_t)item * kItemEdges + lane];
+        jl0 = a.itemJ[(size_t)nxt * kItemEdges + lane];
+        el0 = a.itemE[(size_t)nxt * kItemEdges + lane];
       }
-      i = a.itemI[item];
+      i0 = a.itemI[nxt];
     }
-    i = __builtin_amdgcn_readfirstlane(i);
     // Loads are unconditional: a chunk past the row end reads feature 0 and
     // is dropped, an unused slot reads row i and is not stored.
     TG gi[NCH][CH], rj[kItemEdges][NCH][CH];
@@ -1043,22 +1096,22 @@ __device__ __forceinline__ void edge_items_sweep(const EdgeArgs &a, const Blk bl
     }
     EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0};
     if (!a.init && el >= 0) in = edge_prefetch(a.es, el);
-    double mine = 0.0;
+    static_assert(kItemEdges == 8, "wave_sum8 reduces 8 values");
+    double acc[kItemEdges];
 #pragma unroll
     for (int q = 0; q < kItemEdges; ++q) {
-      double acc = 0.0;
+      acc[q] = 0.0;
 #pragma unroll
       for (int c = 0; c < NCH; ++c) {
         const bool ok = lane * NV + c * CH < a.ld;
 #pragma unroll
         for (int v = 0; v < CH; ++v) {
           const double d = ok ? (double)gi[c][v] - (double)rj[q][c][v] : 0.0;
-          acc = fma(d, d, acc);
+          acc[q] = fma(d, d, acc[q]);
         }
       }
-      acc = wave_sum(acc);
-      mine = (lane == q) ? acc : mine;
     }
+    const double mine = wave_sum8(acc);
     if (el >= 0) edge_update(a.es, el, mine, in, a.init, pa, sc, t3);
   }
   if (a.init) return;
@@ -1407,15 +1460,16 @@ struct Launch {
   int blocks, chunk, nitems;
 };
 
-// Grid for a sweep over nitems wave-items with `waves` waves per block: at
-// most kMaxBlocks blocks, a multiple of the XCD count, each block owning a
-// contiguous chunk.
-static Launch sweep_grid(int64_t nitems, int waves = kWavesPerBlock) {
+// Grid for a sweep over nitems wave-items with `waves` waves per block and
+// about ipw items per wave: at most kMaxBlocks blocks, a multiple of the XCD
+// count, each block owning a contiguous chunk.
+static Launch sweep_grid(int64_t nitems, int waves = kWavesPerBlock, int ipw = 1) {
   Launch L;
   L.nitems = (int)nitems;
-  int64_t want = cdiv(std::max<int64_t>(nitems, 1), waves);
+  int64_t want = cdiv(std::max<int64_t>(nitems, 1), (int64_t)waves * ipw);
   int64_t blocks = std::min<int64_t>(want, kMaxBlocks);
-  blocks = cdiv(blocks, kXcds) * kXcds;
+  // a multiple of the XCD count unless that would at least double the grid
+  if (blocks > kXcds) blocks = cdiv(blocks, kXcds) * kXcds;
   L.blocks = (int)blocks;
   L.chunk = (int)cdiv(std::max<int64_t>(nitems, 1), blocks);
   return L;
@@ -1446,8 +1500,13 @@ static PointArgs point_args(Problem *P, const Launch &Lp) {
 
 template <int PREC, int VEC>
 static void launch_point_t(Problem *P, const Launch &Lp) {
-  hipLaunchKernelGGL((k_point<PREC, VEC>), dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream,
-                     point_args(P, Lp));
+  // prefetching pays when a wave has more than one item
+  if (Lp.chunk > kPointWaves)
+    hipLaunchKernelGGL((k_point<PREC, VEC, true>), dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream,
+                       point_args(P, Lp));
+  else
+    hipLaunchKernelGGL((k_point<PREC, VEC, false>), dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream,
+                       point_args(P, Lp));
 }
 
 static EdgeState edge_state(Problem *P) {
@@ -1474,13 +1533,15 @@ static Launch edge_fused_grid(int64_t E) {
   return L;
 }
 
-// Grid of the item edge kernel: one item per wave, at most kEsumRows blocks.
-static Launch edge_items_grid(int64_t n_items) {
+// Grid of the item edge kernel: about ipw items per wave, at most kEsumRows
+// blocks.
+static Launch edge_items_grid(int64_t n_items, int ipw = 1) {
   Launch L;
   const int64_t nitems = std::max<int64_t>(n_items, 1);
   L.nitems = (int)n_items;
-  int64_t blocks = std::min<int64_t>(cdiv(nitems, kEdgeWaves), kEsumRows);
-  blocks = std::min<int64_t>(cdiv(blocks, kXcds) * kXcds, kEsumRows);
+  int64_t blocks = std::min<int64_t>(cdiv(nitems, (int64_t)kEdgeWaves * ipw), kEsumRows);
+  // a multiple of the XCD count unless that would at least double the grid
+  if (blocks > kXcds) blocks = std::min<int64_t>(cdiv(blocks, kXcds) * kXcds, kEsumRows);
   L.blocks = (int)blocks;
   L.chunk = (int)cdiv(nitems, blocks);
   return L;
@@ -1493,14 +1554,14 @@ static int edge_reduce_blocks(int64_t E) {
 
 // Partial rows the edge stage leaves for the next point sweep.
 static int edge_rows(Problem *P) {
-  if (P->eitems) return edge_items_grid(P->n_items).blocks;
+  if (P->eitems) return edge_items_grid(P->n_items, P->ipw).blocks;
   return P->efused ? edge_fused_grid(P->E).blocks : edge_reduce_blocks(P->E);
 }
 
 template <int PREC>
 static void launch_edge_p(Problem *P, int init, int nbp) {
   if (P->eitems) {
-    const Launch Li = edge_items_grid(P->n_items);
+    const Launch Li = edge_items_grid(P->n_items, P->ipw);
     const EdgeArgs ea = edge_args(P, Li, init, nbp);
     switch (P->item_nv) {
       case 1: hipLaunchKernelGGL((k_edge_items<PREC, 1>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
@@ -1568,7 +1629,7 @@ static void set_slab_attr() {
 // Blocks of the point sweep (its partials count).
 static int point_blocks(Problem *P) {
   if (P->slab_f > 0) return (int)(cdiv(P->ntile * cdiv(P->n, kBlock), kXcds) * kXcds);
-  return sweep_grid(P->n * P->ntile, kPointWaves).blocks;
+  return sweep_grid(P->n * P->ntile, kPointWaves, P->ipw).blocks;
 }
 
 template <int PREC>
@@ -1595,7 +1656,7 @@ static void launch_point_p(Problem *P, const Launch &Lp) {
 static void launch_iteration(Problem *P) {
   hipEvent_t *ev = prof_slot(P);
   if (ev) (void)hipEventRecord(ev[0], P->stream);
-  const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves);
+  const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves, P->ipw);
   const int nbp = point_blocks(P);
   if (P->precision == kF32) launch_point_p<kF32>(P, Lp);
   else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
@@ -2223,14 +2284,20 @@ __global__ void k_batch_done_ticks(int n_inst, const BatchInst *bi, unsigned lon
   if (b < n_inst) out[b] = *bi[b].t_done;
 }
 
-template <int PREC>
-static void launch_batch_point_p(Batch *B, int par) {
+template <int PREC, bool PF>
+static void launch_batch_point_pf(Batch *B, int par) {
   const dim3 g(B->nblk_point), t(kPointBlock);
   switch (B->vec) {
-    case 1: hipLaunchKernelGGL((k_point_batch<PREC, 1>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
-    case 2: hipLaunchKernelGGL((k_point_batch<PREC, 2>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
-    default: hipLaunchKernelGGL((k_point_batch<PREC, 4>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
+    case 1: hipLaunchKernelGGL((k_point_batch<PREC, 1, PF>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
+    case 2: hipLaunchKernelGGL((k_point_batch<PREC, 2, PF>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
+    default: hipLaunchKernelGGL((k_point_batch<PREC, 4, PF>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
   }
+}
+
+template <int PREC>
+static void launch_batch_point_p(Batch *B, int par) {
+  if (B->prefetch) launch_batch_point_pf<PREC, true>(B, par);
+  else launch_batch_point_pf<PREC, false>(B, par);
 }
 
 template <int PREC>
@@ -2262,10 +2329,13 @@ static cc_status upload(T **dst, const std::vector<T> &v, hipStream_t st) {
   return CC_OK;
 }
 
-// Tile shape vec for every instance: block tables, per-instance arguments for
-// both scalar-slot parities, and the graph of graph_iters iterations.
-static cc_status batch_configure(Batch *B, int vec) {
+// Tile shape vec and items per wave ipw (waves with several items prefetch
+// the next one) for every instance: block tables, per-instance arguments
+// for both scalar-slot parities, and the graph of graph_iters iterations.
+static cc_status batch_configure(Batch *B, int vec, int ipw) {
   B->vec = vec;
+  B->ipw = ipw;
+  B->prefetch = ipw > 1;
   B->nv = 1;
   const int n_inst = (int)B->probs.size();
   std::vector<PointArgs> pa[2];
@@ -2278,8 +2348,10 @@ static cc_status batch_configure(Batch *B, int vec) {
     P->ntile = (int)cdiv(P->ld, P->tile_w);
     P->cur_K = B->opts.test_every;
     B->nv = std::max(B->nv, P->item_nv);
-    const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves);
-    const Launch Li = edge_items_grid(P->n_items);
+    P->ipw = B->ipw;
+    P->nbe = edge_rows(P);
+    const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves, P->ipw);
+    const Launch Li = edge_items_grid(P->n_items, P->ipw);
     pblocks[b] = Lp.blocks;
     eblocks[b] = Li.blocks;
     for (int par = 0; par < 2; ++par) {
@@ -2333,6 +2405,11 @@ static cc_status batch_start(Batch *B) {
   CC_HIP(hipGetLastError());
   return CC_OK;
 }
+
+// Autotuner candidates: (vec, items per wave) = (1,1), (1,4), (1,16), (2,1), ...
+constexpr int kTuneConfigs = 9;
+static int tune_vec(int c) { return 1 << (c / 3); }
+static int tune_ipw(int c) { return c % 3 == 0 ? 1 : (c % 3 == 1 ? 4 : 16); }
 
 static cc_status check_opts(const cc_solve_opts &o) {
   if (o.max_iter < 1) { set_error("max_iter must be >= 1"); return CC_ERR_INVALID_ARG; }
@@ -2462,26 +2539,26 @@ cc_status batch_create(int32_t n_inst, Problem *const *probs, const int32_t *n_g
   });
 
   if (autotune) {
-    // point-sweep tile widths 64, 128 and 256 features: time a few graph
-    // replays of each from the instances' initial states
+    // point-sweep tile widths 64, 128 and 256 features, each with 1, 4 and
+    // 16 items per wave: time a few graph replays of each from the
+    // instances' initial states and keep the fastest
     double best = 1e300;
-    int best_vec = 4;
-    B->tune_us.assign(3, 0.0);
-    const int vecs[3] = {1, 2, 4};
-    for (int c = 0; c < 3; ++c) {
+    int best_c = 0;
+    B->tune_us.assign(kTuneConfigs, 0.0);
+    for (int c = 0; c < kTuneConfigs; ++c) {
       for (Problem *P : B->probs) CC_TRY(reset_state(P));
-      CC_TRY(batch_configure(B, vecs[c]));
+      CC_TRY(batch_configure(B, tune_vec(c), tune_ipw(c)));
       double us = 0.0;
       CC_TRY(batch_time(B, 2, &us));
       B->tune_us[c] = us;
-      if (us < best) { best = us; best_vec = vecs[c]; }
+      if (us < best) { best = us; best_c = c; }
     }
     for (Problem *P : B->probs) CC_TRY(reset_state(P));
-    CC_TRY(batch_configure(B, best_vec));
+    CC_TRY(batch_configure(B, tune_vec(best_c), tune_ipw(best_c)));
   } else {
     int64_t maxld = 0;
     for (Problem *P : B->probs) maxld = std::max<int64_t>(maxld, P->ld);
-    CC_TRY(batch_configure(B, maxld > 128 ? 4 : (maxld > 64 ? 2 : 1)));
+    CC_TRY(batch_configure(B, maxld > 128 ? 4 : (maxld > 64 ? 2 : 1), 1));
   }
   guard.ok = true;
   *out = B;

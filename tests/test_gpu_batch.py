@@ -71,7 +71,8 @@ def test_batch_mixed_shapes_autotuned(cc):
     probs = [make(cc, X, e, w) for X, e, w, _ in inst]
     with cc.Batch(probs, [g for *_, g in inst], autotune=True, **OPTS) as bt:
         cfg = bt.config()
-        assert cfg["vec"] in (1, 2, 4) and all(t > 0 for t in cfg["tune_us"])
+        assert cfg["vec"] in (1, 2, 4) and cfg["items_per_wave"] in (1, 4, 16)
+        assert len(cfg["tune_us"]) == 9 and all(t > 0 for t in cfg["tune_us"])
         labs, infos, lat = bt.run()
     for b, (pr, (rinf, rlab, rU, rA, rs)) in enumerate(zip(probs, ref)):
         U = pr.get_state()[0].cpu().numpy()

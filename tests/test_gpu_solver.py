@@ -271,6 +271,18 @@ def test_edge_sweep_variants(cc, p, precision, items, monkeypatch):
     assert rel_max(A, st.A) < tol
 
 
+def test_point_sweep_prefetch(cc):
+    """More point-tile items than one per wave (3000 points x 3 tiles): the
+    point sweep prefetches each wave's next item; trajectory parity."""
+    X, M, E, w, _ = reduced_expression(n=3000, p=700)
+    st, _ = oracle_jacobi(X, M, E, w).solve(5.0, mm.Opts(tol=0, max_iter=12, proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, "f64") as g:
+        g.solve(5.0, tol=0.0, max_iter=12)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    assert rel_max(U, st.U) < 1e-11
+    assert rel_max(A, st.A) < 1e-11
+
+
 @pytest.mark.parametrize("edge_slab", ["0", "1"])
 def test_wide_rows_edge_variants(cc, edge_slab, monkeypatch):
     """Wide rows: the per-tile edge partials (CCMI_EDGE_SLAB=0) and the LDS
