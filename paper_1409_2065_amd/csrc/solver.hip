@@ -332,6 +332,34 @@ struct EdgeArgs {
   const DevScalars *sc; // scalars of the iteration in progress
 };
 
+// Batched launches read their argument blocks from global memory, so the
+// compiler cannot tell that the pointers in them address global memory and
+// would use flat loads, which also count against the LDS wait counter and so
+// serialise with the wave shuffles.  Rebuilding each pointer from its bits
+// in the global address space restores global loads and stores.
+template <typename T>
+__device__ inline void to_global(T *&p) {
+  using G = __attribute__((address_space(1))) T;
+  p = (T *)(G *)(uintptr_t)p;
+}
+
+__device__ inline void globalize(PointArgs &a) {
+  to_global(a.X); to_global(a.M); to_global(a.U); to_global(a.A0); to_global(a.A1);
+  to_global(a.G0); to_global(a.G1); to_global(a.Usnap); to_global(a.Asnap);
+  to_global(a.degE); to_global(a.colE); to_global(a.eidE); to_global(a.qE); to_global(a.s);
+  to_global(a.psum); to_global(a.esum); to_global(a.trace); to_global(a.sin); to_global(a.sout);
+  to_global(a.bi);
+}
+
+__device__ inline void globalize(EdgeArgs &a) {
+  to_global(a.G0); to_global(a.G1); to_global(a.ei); to_global(a.ej);
+  to_global(a.itemI); to_global(a.itemJ); to_global(a.itemE);
+  to_global(a.rowptr); to_global(a.uptr); to_global(a.col); to_global(a.eid); to_global(a.part);
+  to_global(a.es.w); to_global(a.es.s); to_global(a.es.nb0); to_global(a.es.nb1);
+  to_global(a.es.qe); to_global(a.es.qE); to_global(a.es.epos);
+  to_global(a.esum); to_global(a.psum); to_global(a.sc);
+}
+
 struct ReduceArgs {
   int ntile, nbp, init;
   const double *part;
@@ -699,9 +727,11 @@ __global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
 
 // Batched: block q works for instance tab[q].x as its local block tab[q].y.
 template <int PREC, int VEC, bool PF>
-__global__ __launch_bounds__(kPointBlock) void k_point_batch(const PointArgs *args, const int2 *tab) {
+__global__ __launch_bounds__(kPointBlock) void k_point_batch(const PointArgs *__restrict__ args,
+                                                              const int2 *__restrict__ tab) {
   const int2 t = tab[blockIdx.x];
-  const PointArgs a = args[t.x];
+  PointArgs a = args[t.x];
+  globalize(a);
   point_sweep<PREC, VEC, PF, true>(a, Blk{t.y, a.nblk, xcd_remap(t.y, a.nblk)});
 }
 
@@ -1125,9 +1155,11 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_items(EdgeArgs a) {
 
 // Batched: block q works for instance tab[q].x as its local block tab[q].y.
 template <int PREC, int NV>
-__global__ __launch_bounds__(kEdgeBlock) void k_edge_items_batch(const EdgeArgs *args, const int2 *tab) {
+__global__ __launch_bounds__(kEdgeBlock) void k_edge_items_batch(const EdgeArgs *__restrict__ args,
+                                                                  const int2 *__restrict__ tab) {
   const int2 t = tab[blockIdx.x];
-  const EdgeArgs a = args[t.x];
+  EdgeArgs a = args[t.x];
+  globalize(a);
   edge_items_sweep<PREC, NV>(a, Blk{t.y, a.nblk, xcd_remap(t.y, a.nblk)});
 }
 
