@@ -73,6 +73,7 @@ enum { CC_PREC_F32 = 0, CC_PREC_MIXED = 1, CC_PREC_F64 = 2 };
 
 typedef struct cc_problem *cc_problem_t;
 typedef struct cc_batch *cc_batch_t;
+typedef struct cc_server *cc_server_t;
 
 /* Solver options.  Fill with cc_default_opts() and then change fields.
  *   eta         accuracy knob: eps = (eta * rho)^2 when eps <= 0.  The MM
@@ -291,7 +292,7 @@ cc_status cc_components(int64_t n, int64_t n_edges, const int32_t *ei,
  * objective and stopping test, and moves to its next gamma on the device.
  *
  * cc_batch_create: problems[0..n_inst-1] (host array of handles, distinct,
- * same precision, p <= 512, or p <= 256 in FP64); n_gamma (host, n_inst
+ * same precision, p <= 1024); n_gamma (host, n_inst
  * entries >= 1) and gammas (host, the paths one after another, each value
  * finite and >= 0).  opts may be NULL (defaults); each gamma is solved as
  * cc_solve would with these options, warm-started from the previous one
@@ -329,6 +330,58 @@ cc_status cc_batch_run(cc_batch_t batch, int32_t *labels, cc_solve_info *infos,
 cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *items_per_wave,
                           int32_t *graph_iters, double *tune_us);
 cc_status cc_batch_destroy(cc_batch_t batch);
+
+/* ---------------------------------------------------------------------
+ * Served solves (continuous batching)
+ * ---------------------------------------------------------------------
+ * Requests (a data matrix, its kNN weight parameters and a gamma path)
+ * queue on the host and are admitted first come, first served while the
+ * device bytes of the admitted requests stay within hbm_budget (a request
+ * is admitted alone whatever its size).  Admission builds the weights
+ * (cc_build_knn_weights) and the problem on the device; every admitted
+ * request then shares the launches of the others, as in a batch, and
+ * leaves them when its path is done; requests arriving meanwhile join at
+ * the next round.  Each path is solved as cc_solve_path would solve it.
+ *
+ * cc_server_create: precision CC_PREC_*; opts may be NULL (defaults);
+ * max_active (1..4096) admitted requests at most; round_iters (even, >= 2)
+ * MM iterations per cc_server_step; all work on stream.
+ * cc_server_submit: host inputs, copied: X (float32, n rows of p, p <=
+ * 1024, 2 <= n <= 16384), mask (uint8, 1 = observed, may be NULL), k and
+ * phi as for cc_build_knn_weights, gammas (n_gamma >= 1 values).  *ticket
+ * identifies the request.
+ * cc_server_step: admits what the budget allows, then runs one round over
+ * the admitted requests and waits for it.  Host outputs (may be NULL): the
+ * admitted and waiting counts after the round and the number of requests
+ * that finished in it.
+ * cc_server_status: state (CC_REQ_*) and times in seconds since the server
+ * was created: submitted, admitted, done (host clock; done is the end of
+ * the round that finished the path).
+ * cc_server_result: for a CC_REQ_DONE request, labels (device int32,
+ * n_gamma rows of n, may be NULL), infos (host, n_gamma, may be NULL;
+ * seconds = admission to done) as cc_solve_path gives them, and U (device
+ * float32, n rows of p, may be NULL): the centres at the end of the path.
+ * cc_server_release: frees a request that is not running (its budget share
+ * returns).  cc_server_destroy frees every request. */
+#define CC_REQ_WAITING 0
+#define CC_REQ_ACTIVE 1
+#define CC_REQ_DONE 2
+#define CC_REQ_FAILED 3
+cc_status cc_server_create(int32_t precision, const cc_solve_opts *opts,
+                           int64_t hbm_budget, int32_t max_active,
+                           int32_t round_iters, void *stream, cc_server_t *out);
+cc_status cc_server_submit(cc_server_t server, int64_t n, int64_t p,
+                           const float *X, const uint8_t *mask, int32_t k,
+                           double phi, int32_t n_gamma, const double *gammas,
+                           int64_t *ticket);
+cc_status cc_server_step(cc_server_t server, int32_t *n_active,
+                         int32_t *n_waiting, int32_t *n_done);
+cc_status cc_server_status(cc_server_t server, int64_t ticket, int32_t *state,
+                           double *t_submit, double *t_admit, double *t_done);
+cc_status cc_server_result(cc_server_t server, int64_t ticket, int32_t *labels,
+                           cc_solve_info *infos, float *U);
+cc_status cc_server_release(cc_server_t server, int64_t ticket);
+cc_status cc_server_destroy(cc_server_t server);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,7 @@ that takes torch device tensors.  Build with
 ``python -m paper_1409_2065_amd.build``.
 """
 from ._lib import CCError, LIB_PATH, load  # noqa: F401
-from .api import PRECISIONS, Batch, Problem, build_knn_weights, components, standardize_columns  # noqa: F401
+from .api import PRECISIONS, Batch, Problem, Server, build_knn_weights, components, standardize_columns  # noqa: F401
 
-__all__ = ["Problem", "Batch", "build_knn_weights", "standardize_columns", "components", "CCError",
+__all__ = ["Problem", "Batch", "Server", "build_knn_weights", "standardize_columns", "components", "CCError",
            "PRECISIONS", "load", "LIB_PATH"]

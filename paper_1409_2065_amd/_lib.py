@@ -84,7 +84,16 @@ SIGNATURES = {
     "cc_batch_run": (i32, [vp, vp, C.POINTER(SolveInfo), P_f64]),
     "cc_batch_config": (i32, [vp, P_i32, P_i32, P_i32, P_f64]),
     "cc_batch_destroy": (i32, [vp]),
+    "cc_server_create": (i32, [i32, C.POINTER(SolveOpts), i64, i32, i32, vp, C.POINTER(vp)]),
+    "cc_server_submit": (i32, [vp, i64, i64, vp, vp, i32, f64, i32, P_f64, P_i64]),
+    "cc_server_step": (i32, [vp, P_i32, P_i32, P_i32]),
+    "cc_server_status": (i32, [vp, i64, P_i32, P_f64, P_f64, P_f64]),
+    "cc_server_result": (i32, [vp, i64, vp, C.POINTER(SolveInfo), vp]),
+    "cc_server_release": (i32, [vp, i64]),
+    "cc_server_destroy": (i32, [vp]),
 }
+
+CC_REQ_WAITING, CC_REQ_ACTIVE, CC_REQ_DONE, CC_REQ_FAILED = range(4)
 
 _lib = None
 

@@ -294,3 +294,71 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Server:
+    """Continuous-batching solver (cc_server_*): requests (host data, kNN
+    parameters and a gamma path) are admitted first come, first served
+    within an HBM budget and share the launches of the admitted others."""
+
+    def __init__(self, precision: str = "mixed", hbm_budget: int = 8 << 30, max_active: int = 256,
+                 round_iters: int = 32, **opts):
+        o = default_opts(**opts)
+        h = C.c_void_p()
+        check(_lib.load().cc_server_create(PRECISIONS[precision], C.byref(o), int(hbm_budget), int(max_active),
+                                           int(round_iters), C.c_void_p(_stream()), C.byref(h)))
+        self._h = h
+        self._shape = {}
+
+    def submit(self, X, mask=None, k: int = 10, phi: float = -0.5, gammas=(1.0,)) -> int:
+        Xh = np.ascontiguousarray(np.nan_to_num(np.asarray(X, dtype=np.float32)))
+        n, p = Xh.shape
+        mh = None if mask is None else np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+        t = C.c_int64()
+        check(_lib.load().cc_server_submit(self._h, n, p, Xh.ctypes.data_as(C.c_void_p),
+                                           None if mh is None else mh.ctypes.data_as(C.c_void_p),
+                                           int(k), float(phi), g.size, g.ctypes.data_as(_lib.P_f64),
+                                           C.byref(t)))
+        self._shape[t.value] = (n, p, g.size)
+        return t.value
+
+    def step(self):
+        a, w, d = C.c_int32(), C.c_int32(), C.c_int32()
+        check(_lib.load().cc_server_step(self._h, C.byref(a), C.byref(w), C.byref(d)))
+        return a.value, w.value, d.value
+
+    def status(self, ticket: int) -> dict:
+        st = C.c_int32()
+        ts, ta, td = C.c_double(), C.c_double(), C.c_double()
+        check(_lib.load().cc_server_status(self._h, ticket, C.byref(st), C.byref(ts), C.byref(ta), C.byref(td)))
+        return {"state": st.value, "t_submit": ts.value, "t_admit": ta.value, "t_done": td.value}
+
+    def result(self, ticket: int, U: bool = False):
+        n, p, g = self._shape[ticket]
+        lab = torch.empty((g, n), dtype=torch.int32, device="cuda")
+        infos = (_lib.SolveInfo * g)()
+        u = torch.empty((n, p), dtype=torch.float32, device="cuda") if U else None
+        check(_lib.load().cc_server_result(self._h, ticket, _ptr(lab), infos, _ptr(u)))
+        return lab, [infos[k].as_dict() for k in range(g)], u
+
+    def release(self, ticket: int) -> None:
+        check(_lib.load().cc_server_release(self._h, ticket))
+        self._shape.pop(ticket, None)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().cc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

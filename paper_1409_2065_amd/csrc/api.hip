@@ -196,8 +196,8 @@ cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *items_per_wav
   CC_GUARD_BEGIN
   if (!batch) { set_error("batch is NULL"); return CC_ERR_INVALID_ARG; }
   const Batch *B = reinterpret_cast<const Batch *>(batch);
-  if (vec) *vec = B->vec;
-  if (items_per_wave) *items_per_wave = B->ipw;
+  if (vec) *vec = B->ls.vec;
+  if (items_per_wave) *items_per_wave = B->ls.ipw;
   if (graph_iters) *graph_iters = B->graph_iters;
   if (tune_us)
     for (int c = 0; c < 9; ++c) tune_us[c] = c < (int)B->tune_us.size() ? B->tune_us[c] : 0.0;
@@ -208,6 +208,82 @@ cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *items_per_wav
 cc_status cc_batch_destroy(cc_batch_t batch) {
   CC_GUARD_BEGIN
   batch_free(reinterpret_cast<Batch *>(batch));
+  return CC_OK;
+  CC_GUARD_END
+}
+
+cc_status cc_server_create(int32_t precision, const cc_solve_opts *opts, int64_t hbm_budget,
+                           int32_t max_active, int32_t round_iters, void *stream, cc_server_t *out) {
+  CC_GUARD_BEGIN
+  if (!opts_ok(opts)) { set_error("opts->struct_size mismatch"); return CC_ERR_INVALID_ARG; }
+  Server *S = nullptr;
+  cc_status s = server_create(precision, resolve(opts), hbm_budget, max_active, round_iters,
+                              (hipStream_t)stream, &S);
+  if (s != CC_OK) return s;
+  *out = reinterpret_cast<cc_server_t>(S);
+  return CC_OK;
+  CC_GUARD_END
+}
+
+cc_status cc_server_submit(cc_server_t server, int64_t n, int64_t p, const float *X, const uint8_t *mask,
+                           int32_t k, double phi, int32_t n_gamma, const double *gammas, int64_t *ticket) {
+  CC_GUARD_BEGIN
+  if (!server) { set_error("server is NULL"); return CC_ERR_INVALID_ARG; }
+  return server_submit(reinterpret_cast<Server *>(server), n, p, X, mask, k, phi, n_gamma, gammas, ticket);
+  CC_GUARD_END
+}
+
+cc_status cc_server_step(cc_server_t server, int32_t *n_active, int32_t *n_waiting, int32_t *n_done) {
+  CC_GUARD_BEGIN
+  if (!server) { set_error("server is NULL"); return CC_ERR_INVALID_ARG; }
+  return server_step(reinterpret_cast<Server *>(server), n_active, n_waiting, n_done);
+  CC_GUARD_END
+}
+
+cc_status cc_server_status(cc_server_t server, int64_t ticket, int32_t *state, double *t_submit,
+                           double *t_admit, double *t_done) {
+  CC_GUARD_BEGIN
+  if (!server) { set_error("server is NULL"); return CC_ERR_INVALID_ARG; }
+  Request *R = server_find(reinterpret_cast<Server *>(server), ticket);
+  if (!R) { set_error("unknown ticket"); return CC_ERR_INVALID_ARG; }
+  if (state) *state = R->state;
+  if (t_submit) *t_submit = R->t_submit;
+  if (t_admit) *t_admit = R->t_admit;
+  if (t_done) *t_done = R->t_done;
+  return CC_OK;
+  CC_GUARD_END
+}
+
+cc_status cc_server_result(cc_server_t server, int64_t ticket, int32_t *labels, cc_solve_info *infos,
+                           float *U) {
+  CC_GUARD_BEGIN
+  if (!server) { set_error("server is NULL"); return CC_ERR_INVALID_ARG; }
+  Server *S = reinterpret_cast<Server *>(server);
+  Request *R = server_find(S, ticket);
+  if (!R) { set_error("unknown ticket"); return CC_ERR_INVALID_ARG; }
+  cc_status s = server_result(S, R, labels, infos);
+  if (U && R->state == CC_REQ_DONE) {
+    cc_status su = copy_U(R->P, CC_DTYPE_F32, U, R->p);
+    if (su != CC_OK) return su;
+    if (hipStreamSynchronize(S->stream) != hipSuccess) { set_error("stream sync failed"); return CC_ERR_HIP; }
+  }
+  return s;
+  CC_GUARD_END
+}
+
+cc_status cc_server_release(cc_server_t server, int64_t ticket) {
+  CC_GUARD_BEGIN
+  if (!server) { set_error("server is NULL"); return CC_ERR_INVALID_ARG; }
+  Server *S = reinterpret_cast<Server *>(server);
+  Request *R = server_find(S, ticket);
+  if (!R) { set_error("unknown ticket"); return CC_ERR_INVALID_ARG; }
+  return server_release(S, R);
+  CC_GUARD_END
+}
+
+cc_status cc_server_destroy(cc_server_t server) {
+  CC_GUARD_BEGIN
+  server_free(reinterpret_cast<Server *>(server));
   return CC_OK;
   CC_GUARD_END
 }

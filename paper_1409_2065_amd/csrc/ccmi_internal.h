@@ -136,22 +136,33 @@ struct Problem {
 struct PointArgs;  // kernel argument blocks (solver.hip)
 struct EdgeArgs;
 
+// Launch tables of problems that share launches: one point-sweep launch
+// (tile width 64 * vec) and one item edge-sweep launch per features-per-lane
+// class; block -> (instance, local block) tables and per-instance argument
+// blocks for both scalar-slot parities.
+struct EdgeClass {
+  int nv = 1, nblk = 0;
+  EdgeArgs *eargs[2] = {nullptr, nullptr};
+  int2 *etab = nullptr;
+};
+struct LaunchSet {
+  int vec = 4;                    // point-sweep features per lane (all instances)
+  int ipw = 1;                    // about this many items per wave in both sweeps
+  int nblk_point = 0;
+  PointArgs *pargs[2] = {nullptr, nullptr};
+  int2 *ptab = nullptr;
+  std::vector<EdgeClass> ecls;
+};
+
 // Many problems solved along their own gamma paths in the same launches.
 struct Batch {
   std::vector<Problem *> probs;   // not owned
   int precision = kMixed;
-  int vec = 4;                    // point-sweep features per lane (all instances)
-  int ipw = 1;                    // items per wave in both sweeps
-  bool prefetch = false;          // point sweep prefetches each next item (ipw > 1)
-  int nv = 4;                     // edge-sweep features per lane (all instances)
+  LaunchSet ls;
   int graph_iters = 32;           // MM iterations per graph replay (even)
   cc_solve_opts opts{};
   hipStream_t stream = nullptr;   // private: graphs are captured on it
   std::vector<int> order;         // instances by decreasing work
-  int nblk_point = 0, nblk_edge = 0;
-  PointArgs *pargs[2] = {nullptr, nullptr};  // per instance, by scalar slot parity
-  EdgeArgs *eargs[2] = {nullptr, nullptr};
-  int2 *ptab = nullptr, *etab = nullptr;     // block -> (instance, local block)
   BatchInst *bi = nullptr;
   std::vector<int> n_gamma;
   std::vector<int64_t> goff;      // first (instance, gamma) slot of each instance
@@ -201,6 +212,60 @@ cc_status harvest_profile(Problem *P);
 cc_status components(int64_t n, int64_t E, const int32_t *ei,
                      const int32_t *ej, const uint8_t *keep, const double *s,
                      int32_t *labels, int32_t *ncl_dev, hipStream_t stream);
+
+// Served solves: requests queue on the host, are admitted while the HBM
+// budget allows, and share launches with the other admitted requests.
+struct Request {
+  int64_t ticket = 0;
+  int state = 0;                   // CC_REQ_*
+  int64_t n = 0, p = 0;
+  int32_t k = 10;
+  double phi = -0.5;
+  std::vector<float> X;            // host copies until admission
+  std::vector<uint8_t> mask;
+  std::vector<double> gammas, rho, eps, thr;
+  Problem *P = nullptr;            // owned once admitted
+  int64_t footprint = 0;           // bytes counted against the budget
+  BatchInst *bi = nullptr;         // device descriptor and its arrays
+  double *gconst = nullptr;
+  uint8_t *fused = nullptr;
+  double *info = nullptr;
+  unsigned long long *tdone = nullptr;
+  std::vector<double> hinfo;       // per-gamma info once done
+  double t_submit = 0, t_admit = 0, t_done = 0;  // seconds since server creation
+  int status = 0;
+};
+
+struct Server {
+  int precision = kMixed;
+  cc_solve_opts opts{};
+  int64_t budget = 0, used = 0;
+  int max_active = 64;
+  int round_iters = 32;            // MM iterations per round (even)
+  int vec = 4, ipw = 4;
+  hipStream_t stream = nullptr;    // not owned
+  LaunchSet ls;
+  bool dirty = false;
+  int64_t next_ticket = 1;
+  std::vector<Request *> waiting;  // FIFO
+  std::vector<Request *> active;
+  std::vector<Request *> all;      // every request not yet released
+  DevScalars **d_sc0 = nullptr;    // slot 0 of each active request
+  int *d_fin = nullptr;
+  int *h_fin = nullptr;            // pinned
+  int *n_finished = nullptr;
+  double t0 = 0;
+};
+
+cc_status server_create(int32_t precision, const cc_solve_opts &o, int64_t budget, int32_t max_active,
+                        int32_t round_iters, hipStream_t stream, Server **out);
+cc_status server_submit(Server *S, int64_t n, int64_t p, const float *X, const uint8_t *mask, int32_t k,
+                        double phi, int32_t n_gamma, const double *gammas, int64_t *ticket);
+cc_status server_step(Server *S, int32_t *n_active, int32_t *n_waiting, int32_t *n_done);
+Request *server_find(Server *S, int64_t ticket);
+cc_status server_result(Server *S, Request *R, int32_t *labels, cc_solve_info *infos);
+cc_status server_release(Server *S, Request *R);
+void server_free(Server *S);
 
 cc_status batch_create(int32_t n_inst, Problem *const *probs, const int32_t *n_gamma,
                        const double *gammas, const cc_solve_opts &o, int32_t autotune,

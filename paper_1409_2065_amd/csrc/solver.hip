@@ -1060,16 +1060,19 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_fused(EdgeArgs a) {
   edge_block_partials(t3, point_partial_sum(pmine, a.psum, a.nbp, blk), a.esum, blk);
 }
 
-// Rows up to 512 wide: one wave per work item of up to kItemEdges edges
+// Rows up to 1024 wide: one wave per work item of up to kItemEdges edges
 // (i, j_q) sharing the lower end i (lists built on the host).  Row i of the
 // new A is loaded once, NV features per lane (the whole row across the
-// wave), and the rows j_q in one batch; each ||a_i - a_j||^2 is a wave sum
-// and lane q finishes edge q.  Per edge one row is gathered instead of two.
+// wave), and the rows j_q in the same passes; each ||a_i - a_j||^2 is a
+// wave sum and lane q finishes edge q.  Per edge one row is gathered
+// instead of two.
 template <int PREC, int NV>
 __device__ __forceinline__ void edge_items_sweep(const EdgeArgs &a, const Blk blk) {
   using TG = typename Traits<PREC>::TG;
   constexpr int CH = NV < 4 ? NV : 4;  // features per load
   constexpr int NCH = NV / CH;
+  constexpr int MAXCH = sizeof(TG) == 8 ? 1 : 2;
+  constexpr int PCH = NCH < MAXCH ? NCH : MAXCH;
   const DevScalars *sc = a.sc;
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -1107,37 +1110,47 @@ __device__ __forceinline__ void edge_items_sweep(const EdgeArgs &a, const Blk bl
       i0 = a.itemI[nxt];
     }
     // Loads are unconditional: a chunk past the row end reads feature 0 and
-    // is dropped, an unused slot reads row i and is not stored.
-    TG gi[NCH][CH], rj[kItemEdges][NCH][CH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int fo = lane * NV + c * CH;
-      RawIO<TG, CH>::load(Gc + (size_t)i * a.ld + (fo < a.ld ? fo : 0), gi[c]);
-    }
+    // is dropped, an unused slot reads row i and is not stored.  Chunks go in
+    // passes of PCH (8 FP32 or 4 FP64 features per lane in flight).
+    int jq[kItemEdges];
 #pragma unroll
     for (int q = 0; q < kItemEdges; ++q) {
-      const int jq = __builtin_amdgcn_readlane(jl, q);
-      const size_t rowq = (size_t)(jq >= 0 ? jq : i) * a.ld;
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const int fo = lane * NV + c * CH;
-        RawIO<TG, CH>::load(Gc + rowq + (fo < a.ld ? fo : 0), rj[q][c]);
-      }
+      const int j = __builtin_amdgcn_readlane(jl, q);
+      jq[q] = j >= 0 ? j : i;
     }
-    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0};
-    if (!a.init && el >= 0) in = edge_prefetch(a.es, el);
     static_assert(kItemEdges == 8, "wave_sum8 reduces 8 values");
     double acc[kItemEdges];
 #pragma unroll
-    for (int q = 0; q < kItemEdges; ++q) {
-      acc[q] = 0.0;
+    for (int q = 0; q < kItemEdges; ++q) acc[q] = 0.0;
+    EdgeIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0};
+#pragma unroll 1
+    for (int c0 = 0; c0 < NCH; c0 += PCH) {
+      TG gi[PCH][CH], rj[kItemEdges][PCH][CH];
 #pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        const bool ok = lane * NV + c * CH < a.ld;
+      for (int c = 0; c < PCH; ++c) {
+        const int fo = lane * NV + (c0 + c) * CH;
+        RawIO<TG, CH>::load(Gc + (size_t)i * a.ld + (fo < a.ld ? fo : 0), gi[c]);
+      }
 #pragma unroll
-        for (int v = 0; v < CH; ++v) {
-          const double d = ok ? (double)gi[c][v] - (double)rj[q][c][v] : 0.0;
-          acc[q] = fma(d, d, acc[q]);
+      for (int q = 0; q < kItemEdges; ++q) {
+        const size_t rowq = (size_t)jq[q] * a.ld;
+#pragma unroll
+        for (int c = 0; c < PCH; ++c) {
+          const int fo = lane * NV + (c0 + c) * CH;
+          RawIO<TG, CH>::load(Gc + rowq + (fo < a.ld ? fo : 0), rj[q][c]);
+        }
+      }
+      if (c0 == 0 && !a.init && el >= 0) in = edge_prefetch(a.es, el);
+#pragma unroll
+      for (int q = 0; q < kItemEdges; ++q) {
+#pragma unroll
+        for (int c = 0; c < PCH; ++c) {
+          const bool ok = lane * NV + (c0 + c) * CH < a.ld;
+#pragma unroll
+          for (int v = 0; v < CH; ++v) {
+            const double d = ok ? (double)gi[c][v] - (double)rj[q][c][v] : 0.0;
+            acc[q] = fma(d, d, acc[q]);
+          }
         }
       }
     }
@@ -1599,11 +1612,8 @@ static void launch_edge_p(Problem *P, int init, int nbp) {
       case 1: hipLaunchKernelGGL((k_edge_items<PREC, 1>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
       case 2: hipLaunchKernelGGL((k_edge_items<PREC, 2>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
       case 4: hipLaunchKernelGGL((k_edge_items<PREC, 4>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      default:
-        // FP64 rows take at most 4 features per lane (register budget)
-        if constexpr (PREC != kF64)
-          hipLaunchKernelGGL((k_edge_items<PREC, 8>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea);
-        break;
+      case 8: hipLaunchKernelGGL((k_edge_items<PREC, 8>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      default: hipLaunchKernelGGL((k_edge_items<PREC, 16>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
     }
     return;
   }
@@ -1798,12 +1808,10 @@ static void choose_tiles(Problem *P) {
   P->tile_w = slab > 0 ? slab : kWave * vec;
   P->ntile = (int)cdiv(P->ld, P->tile_w);
   // edge sweep: work items of edges sharing a lower end when the whole row
-  // fits a wave at 8 features per lane (4 for FP64 rows; CCMI_EDGE_ITEMS=0
-  // turns this off), else one tile over the whole row when it is at most
-  // 1024 wide
+  // fits a wave at up to 16 features per lane (CCMI_EDGE_ITEMS=0 turns this
+  // off), else one tile over the whole row when it is at most 1024 wide
   const char *eit = getenv("CCMI_EDGE_ITEMS");
-  const int64_t item_w = (P->precision == kF64 ? 4 : 8) * kWave;
-  P->eitems = P->ld <= item_w && !(eit && atoi(eit) == 0);
+  P->eitems = P->ld <= 16 * kWave && !(eit && atoi(eit) == 0);
   P->item_nv = 1;
   while (P->item_nv * kWave < P->ld) P->item_nv <<= 1;
   if (P->ld <= 1024) {
@@ -2317,39 +2325,38 @@ __global__ void k_batch_done_ticks(int n_inst, const BatchInst *bi, unsigned lon
 }
 
 template <int PREC, bool PF>
-static void launch_batch_point_pf(Batch *B, int par) {
-  const dim3 g(B->nblk_point), t(kPointBlock);
-  switch (B->vec) {
-    case 1: hipLaunchKernelGGL((k_point_batch<PREC, 1, PF>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
-    case 2: hipLaunchKernelGGL((k_point_batch<PREC, 2, PF>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
-    default: hipLaunchKernelGGL((k_point_batch<PREC, 4, PF>), g, t, 0, B->stream, B->pargs[par], B->ptab); break;
+static void launch_set_point_pf(const LaunchSet &L, int par, hipStream_t st) {
+  const dim3 g(L.nblk_point), t(kPointBlock);
+  switch (L.vec) {
+    case 1: hipLaunchKernelGGL((k_point_batch<PREC, 1, PF>), g, t, 0, st, L.pargs[par], L.ptab); break;
+    case 2: hipLaunchKernelGGL((k_point_batch<PREC, 2, PF>), g, t, 0, st, L.pargs[par], L.ptab); break;
+    default: hipLaunchKernelGGL((k_point_batch<PREC, 4, PF>), g, t, 0, st, L.pargs[par], L.ptab); break;
   }
 }
 
 template <int PREC>
-static void launch_batch_point_p(Batch *B, int par) {
-  if (B->prefetch) launch_batch_point_pf<PREC, true>(B, par);
-  else launch_batch_point_pf<PREC, false>(B, par);
-}
-
-template <int PREC>
-static void launch_batch_edge_p(Batch *B, int par) {
-  const dim3 g(B->nblk_edge), t(kEdgeBlock);
-  switch (B->nv) {
-    case 1: hipLaunchKernelGGL((k_edge_items_batch<PREC, 1>), g, t, 0, B->stream, B->eargs[par], B->etab); break;
-    case 2: hipLaunchKernelGGL((k_edge_items_batch<PREC, 2>), g, t, 0, B->stream, B->eargs[par], B->etab); break;
-    case 4: hipLaunchKernelGGL((k_edge_items_batch<PREC, 4>), g, t, 0, B->stream, B->eargs[par], B->etab); break;
-    default:
-      if constexpr (PREC != kF64)
-        hipLaunchKernelGGL((k_edge_items_batch<PREC, 8>), g, t, 0, B->stream, B->eargs[par], B->etab);
-      break;
+static void launch_set_p(const LaunchSet &L, int par, hipStream_t st) {
+  if (L.nblk_point > 0) {
+    if (L.ipw > 1) launch_set_point_pf<PREC, true>(L, par, st);
+    else launch_set_point_pf<PREC, false>(L, par, st);
+  }
+  for (const EdgeClass &c : L.ecls) {
+    const dim3 g(c.nblk), t(kEdgeBlock);
+    switch (c.nv) {
+      case 1: hipLaunchKernelGGL((k_edge_items_batch<PREC, 1>), g, t, 0, st, c.eargs[par], c.etab); break;
+      case 2: hipLaunchKernelGGL((k_edge_items_batch<PREC, 2>), g, t, 0, st, c.eargs[par], c.etab); break;
+      case 4: hipLaunchKernelGGL((k_edge_items_batch<PREC, 4>), g, t, 0, st, c.eargs[par], c.etab); break;
+      case 8: hipLaunchKernelGGL((k_edge_items_batch<PREC, 8>), g, t, 0, st, c.eargs[par], c.etab); break;
+      default: hipLaunchKernelGGL((k_edge_items_batch<PREC, 16>), g, t, 0, st, c.eargs[par], c.etab); break;
+    }
   }
 }
 
-static void launch_batch_iteration(Batch *B, int par) {
-  if (B->precision == kF32) { launch_batch_point_p<kF32>(B, par); launch_batch_edge_p<kF32>(B, par); }
-  else if (B->precision == kF64) { launch_batch_point_p<kF64>(B, par); launch_batch_edge_p<kF64>(B, par); }
-  else { launch_batch_point_p<kMixed>(B, par); launch_batch_edge_p<kMixed>(B, par); }
+// One MM iteration of every problem of the set (scalar-slot parity par).
+static void launch_set_iteration(const LaunchSet &L, int prec, int par, hipStream_t st) {
+  if (prec == kF32) launch_set_p<kF32>(L, par, st);
+  else if (prec == kF64) launch_set_p<kF64>(L, par, st);
+  else launch_set_p<kMixed>(L, par, st);
 }
 
 template <typename T>
@@ -2361,26 +2368,41 @@ static cc_status upload(T **dst, const std::vector<T> &v, hipStream_t st) {
   return CC_OK;
 }
 
-// Tile shape vec and items per wave ipw (waves with several items prefetch
-// the next one) for every instance: block tables, per-instance arguments
-// for both scalar-slot parities, and the graph of graph_iters iterations.
-static cc_status batch_configure(Batch *B, int vec, int ipw) {
-  B->vec = vec;
-  B->ipw = ipw;
-  B->prefetch = ipw > 1;
-  B->nv = 1;
-  const int n_inst = (int)B->probs.size();
+static void free_launch_set(LaunchSet &L) {
+  void *bufs[] = {L.pargs[0], L.pargs[1], L.ptab};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  for (EdgeClass &c : L.ecls) {
+    void *eb[] = {c.eargs[0], c.eargs[1], c.etab};
+    for (void *b : eb)
+      if (b) (void)hipFree(b);
+  }
+  L = LaunchSet();
+}
+
+// Launch tables for problems probs[k] (device descriptors bis[k]), blocks
+// laid out in the given order of instances: tile shape vec and about ipw
+// items per wave (waves with several items prefetch the next) for every
+// instance, edge launches grouped by each instance's features per lane.
+// Sets the problems' tile fields and scalar slot 0.
+static cc_status build_launch_set(LaunchSet &L, const std::vector<Problem *> &probs,
+                                  const std::vector<const BatchInst *> &bis,
+                                  const std::vector<int> &order, int vec, int ipw, int K,
+                                  hipStream_t st) {
+  free_launch_set(L);
+  L.vec = vec;
+  L.ipw = ipw;
+  const int n_inst = (int)probs.size();
   std::vector<PointArgs> pa[2];
   std::vector<EdgeArgs> ea[2];
   std::vector<int> pblocks(n_inst), eblocks(n_inst);
   for (int b = 0; b < n_inst; ++b) {
-    Problem *P = B->probs[b];
+    Problem *P = probs[b];
     P->vec = vec;
     P->tile_w = kWave * vec;
     P->ntile = (int)cdiv(P->ld, P->tile_w);
-    P->cur_K = B->opts.test_every;
-    B->nv = std::max(B->nv, P->item_nv);
-    P->ipw = B->ipw;
+    P->cur_K = K;
+    P->ipw = ipw;
     P->nbe = edge_rows(P);
     const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves, P->ipw);
     const Launch Li = edge_items_grid(P->n_items, P->ipw);
@@ -2389,33 +2411,47 @@ static cc_status batch_configure(Batch *B, int vec, int ipw) {
     for (int par = 0; par < 2; ++par) {
       P->slot = par;
       PointArgs x = point_args(P, Lp);
-      x.bi = B->bi + b;
+      x.bi = bis[b];
       pa[par].push_back(x);
       P->slot = par ^ 1;
       ea[par].push_back(edge_args(P, Li, 0, Lp.blocks));
     }
     P->slot = 0;
   }
-  std::vector<int2> pt, et;
-  for (int b : B->order) {
+  std::vector<int2> pt;
+  for (int b : order)
     for (int q = 0; q < pblocks[b]; ++q) pt.push_back(make_int2(b, q));
-    for (int q = 0; q < eblocks[b]; ++q) et.push_back(make_int2(b, q));
+  L.nblk_point = (int)pt.size();
+  for (int par = 0; par < 2; ++par) CC_TRY(upload(&L.pargs[par], pa[par], st));
+  CC_TRY(upload(&L.ptab, pt, st));
+  for (int nv : {1, 2, 4, 8, 16}) {
+    std::vector<int2> et;
+    for (int b : order)
+      if (probs[b]->item_nv == nv)
+        for (int q = 0; q < eblocks[b]; ++q) et.push_back(make_int2(b, q));
+    if (et.empty()) continue;
+    EdgeClass c;
+    c.nv = nv;
+    c.nblk = (int)et.size();
+    for (int par = 0; par < 2; ++par) CC_TRY(upload(&c.eargs[par], ea[par], st));
+    CC_TRY(upload(&c.etab, et, st));
+    L.ecls.push_back(c);
   }
-  B->nblk_point = (int)pt.size();
-  B->nblk_edge = (int)et.size();
-  for (int par = 0; par < 2; ++par) {
-    CC_TRY(upload(&B->pargs[par], pa[par], B->stream));
-    CC_TRY(upload(&B->eargs[par], ea[par], B->stream));
-  }
-  CC_TRY(upload(&B->ptab, pt, B->stream));
-  CC_TRY(upload(&B->etab, et, B->stream));
-  CC_HIP(hipStreamSynchronize(B->stream));
+  CC_HIP(hipStreamSynchronize(st));
+  return CC_OK;
+}
+
+// Launch tables and the graph of graph_iters iterations for (vec, ipw).
+static cc_status batch_configure(Batch *B, int vec, int ipw) {
+  std::vector<const BatchInst *> bis;
+  for (size_t b = 0; b < B->probs.size(); ++b) bis.push_back(B->bi + b);
+  CC_TRY(build_launch_set(B->ls, B->probs, bis, B->order, vec, ipw, B->opts.test_every, B->stream));
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   B->gexec = nullptr;
   B->graph = nullptr;
   CC_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-  for (int it = 0; it < B->graph_iters; ++it) launch_batch_iteration(B, it & 1);
+  for (int it = 0; it < B->graph_iters; ++it) launch_set_iteration(B->ls, B->precision, it & 1, B->stream);
   CC_HIP(hipStreamEndCapture(B->stream, &B->graph));
   CC_HIP(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
   return CC_OK;
@@ -2455,8 +2491,8 @@ void batch_free(Batch *B) {
   if (!B) return;
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
-  void *bufs[] = {B->pargs[0], B->pargs[1], B->eargs[0], B->eargs[1], B->ptab, B->etab, B->bi,
-                  B->gconst, B->fused, B->info, B->ticks, B->n_finished, B->ncl};
+  free_launch_set(B->ls);
+  void *bufs[] = {B->bi, B->gconst, B->fused, B->info, B->ticks, B->n_finished, B->ncl};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (B->fin_host) (void)hipHostFree(B->fin_host);
@@ -2497,7 +2533,7 @@ cc_status batch_create(int32_t n_inst, Problem *const *probs, const int32_t *n_g
     if (!P) { set_error("problem " + std::to_string(b) + " is NULL"); return CC_ERR_INVALID_ARG; }
     if (P->precision != probs[0]->precision) { set_error("all problems of a batch need the same precision"); return CC_ERR_INVALID_ARG; }
     if (!P->eitems || P->slab_f > 0) {
-      set_error("problem " + std::to_string(b) + ": rows wider than a batched sweep takes (p <= 512, 256 in FP64)");
+      set_error("problem " + std::to_string(b) + ": rows wider than a batched sweep takes (p <= 1024)");
       return CC_ERR_INVALID_ARG;
     }
     if (n_gamma[b] < 1) { set_error("every instance needs at least one gamma"); return CC_ERR_INVALID_ARG; }
@@ -2665,6 +2701,309 @@ cc_status batch_run(Batch *B, int32_t *labels, cc_solve_info *infos, double *lat
     if (latency_ms) latency_ms[b] = (double)(ticks[1 + b] - ticks[0]) / B->tick_khz;
   }
   return st;
+}
+
+
+// ============================================================ served solves
+// Requests wait on the host until the HBM budget admits them (first come,
+// first served); an admitted request gets its kNN weights and problem on
+// the device and joins the shared launches; rounds of round_iters MM
+// iterations run every admitted request; a request whose path is done on
+// the device leaves the launches, its result stays until released.
+
+__global__ void k_inst_init(const BatchInst *bi, int max_iter, int K) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  DevScalars *sc = bi->sc0;
+  sc->mu = bi->mu[0]; sc->rho = bi->rho[0]; sc->eps = bi->eps[0]; sc->thr = bi->thr[0];
+  sc->max_iter = max_iter; sc->record = 0; sc->K = K;
+  sc->m = 0; sc->done = 0; sc->converged = 0; sc->status = 0; sc->iters = 0;
+  sc->d_prev = 0.0; sc->dA_prev = 0.0; sc->F_cur = 0.0;
+  sc->F_last = 0.0; sc->d_last = 0.0; sc->rel_last = 0.0;
+  sc->pending = 0; sc->path_k = 0; sc->finished = 0;
+}
+
+__global__ void k_gather_finished(int n, DevScalars *const *sc0, int *out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = sc0[k]->finished;
+}
+
+static double host_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device bytes a request will hold: the problem's arrays (edges bounded by
+// n * k, neighbour lists by 2k per point on average) and the per-gamma
+// outputs.
+static int64_t request_bytes(int64_t n, int64_t p, int32_t k, bool mask, int precision, int64_t n_gamma) {
+  const int64_t ld = (p + 3) / 4 * 4;
+  const int64_t ts = precision == kF32 ? 4 : 8, tx = precision == kF64 ? 8 : 4;
+  const int64_t tg = precision == kMixed ? 4 : 0;
+  const int64_t E = n * k;
+  return n * ld * (tx + (mask ? 1 : 0) + 5 * ts + 2 * tg) + E * (128 + n_gamma) + n * 2 * k * 16 +
+         n_gamma * kInfoVals * 8 + (int64_t)kMaxBlocks * 64;
+}
+
+void server_free(Server *S) {
+  if (!S) return;
+  for (Request *R : S->all) {
+    if (R->P) problem_free(R->P);
+    void *bufs[] = {R->bi, R->gconst, R->fused, R->info, R->tdone};
+    for (void *b : bufs)
+      if (b) (void)hipFree(b);
+    delete R;
+  }
+  free_launch_set(S->ls);
+  void *bufs[] = {S->d_sc0, S->d_fin, S->n_finished};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (S->h_fin) (void)hipHostFree(S->h_fin);
+  delete S;
+}
+
+cc_status server_create(int32_t precision, const cc_solve_opts &o, int64_t budget, int32_t max_active,
+                        int32_t round_iters, hipStream_t stream, Server **out) {
+  if (!out) { set_error("out is NULL"); return CC_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (precision != kF32 && precision != kMixed && precision != kF64) { set_error("unknown precision"); return CC_ERR_INVALID_ARG; }
+  if (budget < 1) { set_error("need an HBM budget >= 1 byte"); return CC_ERR_INVALID_ARG; }
+  if (max_active < 1 || max_active > 4096) { set_error("need 1 <= max_active <= 4096"); return CC_ERR_INVALID_ARG; }
+  if (round_iters < 2 || round_iters % 2) { set_error("round_iters must be even and >= 2"); return CC_ERR_INVALID_ARG; }
+  CC_TRY(check_opts(o));
+  Server *S = new (std::nothrow) Server();
+  if (!S) { set_error("host allocation failed"); return CC_ERR_OUT_OF_MEMORY; }
+  struct Guard { Server *&S; bool ok = false; ~Guard() { if (!ok) server_free(S); } } guard{S};
+  S->precision = precision;
+  S->opts = o;
+  S->budget = budget;
+  S->max_active = max_active;
+  S->round_iters = round_iters;
+  S->stream = stream;
+  CC_TRY(dmalloc((void **)&S->d_sc0, (size_t)max_active * sizeof(DevScalars *)));
+  CC_TRY(dmalloc((void **)&S->d_fin, (size_t)max_active * 4));
+  CC_TRY(dmalloc((void **)&S->n_finished, 4));
+  CC_HIP(hipHostMalloc((void **)&S->h_fin, (size_t)max_active * 4, hipHostMallocDefault));
+  S->t0 = host_seconds();
+  guard.ok = true;
+  *out = S;
+  return CC_OK;
+}
+
+cc_status server_submit(Server *S, int64_t n, int64_t p, const float *X, const uint8_t *mask, int32_t k,
+                        double phi, int32_t n_gamma, const double *gammas, int64_t *ticket) {
+  if (n < 2 || p < 1 || !X) { set_error("need n >= 2, p >= 1 and X"); return CC_ERR_INVALID_ARG; }
+  if ((p + 3) / 4 * 4 > 16 * kWave) { set_error("served requests take p <= 1024"); return CC_ERR_INVALID_ARG; }
+  if (n > 16384) { set_error("served requests take n <= 16384"); return CC_ERR_INVALID_ARG; }
+  if (k < 1 || k >= n) { set_error("need 1 <= k < n"); return CC_ERR_INVALID_ARG; }
+  if (!std::isfinite(phi)) { set_error("phi must be finite"); return CC_ERR_INVALID_ARG; }
+  if (n_gamma < 1 || !gammas) { set_error("need at least one gamma"); return CC_ERR_INVALID_ARG; }
+  for (int32_t g = 0; g < n_gamma; ++g)
+    if (!(gammas[g] >= 0.0) || !std::isfinite(gammas[g])) { set_error("gammas must be finite and >= 0"); return CC_ERR_INVALID_ARG; }
+  Request *R = new (std::nothrow) Request();
+  if (!R) { set_error("host allocation failed"); return CC_ERR_OUT_OF_MEMORY; }
+  R->ticket = S->next_ticket++;
+  R->state = CC_REQ_WAITING;
+  R->n = n;
+  R->p = p;
+  R->k = k;
+  R->phi = phi;
+  R->X.assign(X, X + n * p);
+  if (mask) R->mask.assign(mask, mask + n * p);
+  R->gammas.assign(gammas, gammas + n_gamma);
+  R->footprint = request_bytes(n, p, k, mask != nullptr, S->precision, n_gamma);
+  R->t_submit = host_seconds() - S->t0;
+  S->waiting.push_back(R);
+  S->all.push_back(R);
+  if (ticket) *ticket = R->ticket;
+  return CC_OK;
+}
+
+// Weights, problem and device descriptor of a request; its host copies go.
+static cc_status admit(Server *S, Request *R) {
+  const int64_t n = R->n, p = R->p;
+  float *dX = nullptr;
+  uint8_t *dM = nullptr;
+  int32_t *ei = nullptr, *ej = nullptr;
+  double *w = nullptr;
+  struct Tmp {
+    void *b[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    ~Tmp() { for (void *x : b) if (x) (void)hipFree(x); }
+  } tmp;
+  CC_TRY(dmalloc((void **)&dX, n * p * 4));
+  tmp.b[0] = dX;
+  CC_HIP(hipMemcpyAsync(dX, R->X.data(), n * p * 4, hipMemcpyHostToDevice, S->stream));
+  if (!R->mask.empty()) {
+    CC_TRY(dmalloc((void **)&dM, n * p));
+    tmp.b[1] = dM;
+    CC_HIP(hipMemcpyAsync(dM, R->mask.data(), n * p, hipMemcpyHostToDevice, S->stream));
+  }
+  const int64_t cap = n * R->k;
+  CC_TRY(dmalloc((void **)&ei, cap * 4));
+  tmp.b[2] = ei;
+  CC_TRY(dmalloc((void **)&ej, cap * 4));
+  tmp.b[3] = ej;
+  CC_TRY(dmalloc((void **)&w, cap * 8));
+  tmp.b[4] = w;
+  int64_t E = 0;
+  double phi_used = 0.0;
+  CC_TRY(build_knn_weights(n, p, CC_DTYPE_F32, dX, p, dM, p, R->k, R->phi, 0, ei, ej, w, cap, &E,
+                           &phi_used, S->stream));
+  CC_TRY(problem_create(n, p, CC_DTYPE_F32, dX, p, dM, p, E, ei, ej, w, S->precision, S->stream, &R->P));
+  Problem *P = R->P;
+  const int ng = (int)R->gammas.size();
+  R->rho.resize(ng);
+  R->eps.resize(ng);
+  R->thr.resize(ng);
+  for (int g = 0; g < ng; ++g) solve_constants(P, R->gammas[g], S->opts, &R->rho[g], &R->eps[g], &R->thr[g]);
+  std::vector<double> gc;
+  for (const auto *v : {&R->gammas, &R->rho, &R->eps, &R->thr}) gc.insert(gc.end(), v->begin(), v->end());
+  CC_TRY(upload(&R->gconst, gc, S->stream));
+  CC_TRY(dmalloc((void **)&R->fused, std::max<int64_t>((int64_t)ng * P->E, 1)));
+  CC_TRY(dmalloc((void **)&R->info, (size_t)ng * kInfoVals * 8));
+  CC_TRY(dmalloc((void **)&R->tdone, 8));
+  const BatchInst bi{ng, (int)P->E, P->sc, R->gconst, R->gconst + ng, R->gconst + 2 * ng, R->gconst + 3 * ng,
+                     P->s, R->fused, R->info, R->tdone, S->n_finished};
+  CC_TRY(upload(&R->bi, std::vector<BatchInst>{bi}, S->stream));
+  hipLaunchKernelGGL(k_inst_init, dim3(1), dim3(1), 0, S->stream, (const BatchInst *)R->bi, S->opts.max_iter,
+                     S->opts.test_every);
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipStreamSynchronize(S->stream));
+  P->slot = 0;
+  R->X.clear();
+  R->X.shrink_to_fit();
+  R->mask.clear();
+  R->mask.shrink_to_fit();
+  R->state = CC_REQ_ACTIVE;
+  R->t_admit = host_seconds() - S->t0;
+  return CC_OK;
+}
+
+cc_status server_step(Server *S, int32_t *n_active, int32_t *n_waiting, int32_t *n_done) {
+  // admission: first come, first served, while the budget allows (a request
+  // alone on the device is admitted whatever its size)
+  while (!S->waiting.empty() && (int)S->active.size() < S->max_active) {
+    Request *R = S->waiting.front();
+    if (!S->active.empty() && S->used + R->footprint > S->budget) break;
+    S->waiting.erase(S->waiting.begin());
+    cc_status st = admit(S, R);
+    if (st != CC_OK) {
+      R->state = CC_REQ_FAILED;
+      R->status = st;
+      R->t_done = host_seconds() - S->t0;
+      continue;
+    }
+    S->used += R->footprint;
+    S->active.push_back(R);
+    S->dirty = true;
+  }
+  int done_now = 0;
+  if (!S->active.empty()) {
+    const int na = (int)S->active.size();
+    if (S->dirty) {
+      std::vector<Problem *> probs;
+      std::vector<const BatchInst *> bis;
+      std::vector<DevScalars *> sc0;
+      for (Request *R : S->active) {
+        probs.push_back(R->P);
+        bis.push_back(R->bi);
+        sc0.push_back(R->P->sc);
+      }
+      std::vector<int> order(na);
+      std::iota(order.begin(), order.end(), 0);
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return probs[a]->n * probs[a]->ld > probs[b]->n * probs[b]->ld;
+      });
+      CC_TRY(build_launch_set(S->ls, probs, bis, order, S->vec, S->ipw, S->opts.test_every, S->stream));
+      CC_HIP(hipMemcpyAsync(S->d_sc0, sc0.data(), sc0.size() * sizeof(DevScalars *), hipMemcpyHostToDevice, S->stream));
+      S->dirty = false;
+    }
+    for (int it = 0; it < S->round_iters; ++it) launch_set_iteration(S->ls, S->precision, it & 1, S->stream);
+    hipLaunchKernelGGL(k_gather_finished, dim3((int)cdiv(na, 256)), dim3(256), 0, S->stream, na,
+                       (DevScalars *const *)S->d_sc0, S->d_fin);
+    CC_HIP(hipGetLastError());
+    CC_HIP(hipMemcpyAsync(S->h_fin, S->d_fin, (size_t)na * 4, hipMemcpyDeviceToHost, S->stream));
+    CC_HIP(hipStreamSynchronize(S->stream));
+    const double now = host_seconds() - S->t0;
+    std::vector<Request *> still;
+    for (int k = 0; k < na; ++k) {
+      Request *R = S->active[k];
+      if (!S->h_fin[k]) {
+        still.push_back(R);
+        continue;
+      }
+      R->hinfo.resize(R->gammas.size() * kInfoVals);
+      CC_HIP(hipMemcpy(R->hinfo.data(), R->info, R->hinfo.size() * 8, hipMemcpyDeviceToHost));
+      R->state = CC_REQ_DONE;
+      R->t_done = now;
+      for (size_t g = 0; g < R->gammas.size(); ++g)
+        if (R->hinfo[g * kInfoVals + 2] != 0.0) R->status = (int)R->hinfo[g * kInfoVals + 2];
+      ++done_now;
+    }
+    if ((int)still.size() != na) {
+      S->active = still;
+      S->dirty = true;
+    }
+  }
+  if (n_active) *n_active = (int)S->active.size();
+  if (n_waiting) *n_waiting = (int)S->waiting.size();
+  if (n_done) *n_done = done_now;
+  return CC_OK;
+}
+
+Request *server_find(Server *S, int64_t ticket) {
+  for (Request *R : S->all)
+    if (R->ticket == ticket) return R;
+  return nullptr;
+}
+
+cc_status server_result(Server *S, Request *R, int32_t *labels, cc_solve_info *infos) {
+  if (R->state != CC_REQ_DONE) { set_error("request not done"); return CC_ERR_STATE; }
+  Problem *P = R->P;
+  const int ng = (int)R->gammas.size();
+  int32_t *scratch = nullptr;
+  struct Tmp { int32_t *&p; ~Tmp() { if (p) (void)hipFree(p); } } tmp{scratch};
+  if (!labels && infos) CC_TRY(dmalloc((void **)&scratch, P->n * 4));
+  for (int g = 0; g < ng; ++g) {
+    int32_t ncl = 0;
+    if (labels || infos) {
+      CC_TRY(components(P->n, P->E, P->ei, P->ej, R->fused + (int64_t)g * P->E, nullptr,
+                        labels ? labels + (int64_t)g * P->n : scratch, P->ncl_dev, S->stream));
+      CC_HIP(hipMemcpyAsync(P->flag_host, P->ncl_dev, 4, hipMemcpyDeviceToHost, S->stream));
+      CC_HIP(hipStreamSynchronize(S->stream));
+      ncl = P->flag_host[0];
+    }
+    if (infos) {
+      const double *v = &R->hinfo[(size_t)g * kInfoVals];
+      cc_solve_info &in = infos[g];
+      in.iters = (int32_t)v[0];
+      in.converged = (int32_t)v[1];
+      in.n_clusters = ncl;
+      in.status = (int32_t)v[2];
+      in.gamma = R->gammas[g];
+      in.objective = v[3];
+      in.d = v[4];
+      in.rel_change = v[5];
+      in.rho = R->rho[g];
+      in.eps = R->eps[g];
+      in.seconds = R->t_done - R->t_admit;
+    }
+  }
+  return R->status == 0 ? CC_OK : (cc_status)R->status;
+}
+
+cc_status server_release(Server *S, Request *R) {
+  if (R->state == CC_REQ_ACTIVE) { set_error("request still running"); return CC_ERR_STATE; }
+  if (R->state == CC_REQ_WAITING) {
+    S->waiting.erase(std::find(S->waiting.begin(), S->waiting.end(), R));
+  } else if (R->P) {
+    S->used -= R->footprint;
+  }
+  if (R->P) problem_free(R->P);
+  void *bufs[] = {R->bi, R->gconst, R->fused, R->info, R->tdone};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  S->all.erase(std::find(S->all.begin(), S->all.end(), R));
+  delete R;
+  return CC_OK;
 }
 
 }  // namespace ccmi
