@@ -16,6 +16,21 @@ GPU before timing (reported separately).
 Metric: pair-feature updates/s = sum over MM iterations of |E| * p, divided
 by the wall time of the timed steps (inputs resident in HBM).
 
+Beside it, the line carries the batched and served comparisons the metric
+names (solves/s and latency, against the plain per-solve path):
+  batched  256 instances (n ~ U{50..800}, p ~ U{20..200}, 2-10 clusters,
+           kNN k=10, 16 gammas each) in shared launches, tile shape
+           autotuned, each gamma capped at --batch-max-iter MM iterations;
+           the plain path solves the first --plain-sample instances one by
+           one with the same options (its FIFO latency for all 256 is
+           estimated from them and marked so);
+  served   the first --serve-requests requests of the Poisson stream
+           (200/s; n log-uniform in [100, 5000], p in [10, 1000], 10%
+           missing, 8-32 gammas) submitted at their arrival times to the
+           continuous-batching server and, separately, solved first come
+           first served by the plain path; each gamma capped at
+           --serve-max-iter MM iterations.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -31,6 +46,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+METRIC = "pair-feature updates/s (n=2000,p=500); solves/s + p99 latency, batched vs plain"
 
 WORKLOAD_TEXT = {
     "expression": "expression-like n=2000 p=500, 20 clusters, log-normal scales, 5% MCAR, kNN k=15, "
@@ -95,10 +111,127 @@ def cpu_baseline(wl, seconds):
     }
 
 
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q))
+
+
+def bench_batched(args):
+    """Batched instances in shared launches against the plain per-solve path."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1409_2065_amd as cc
+    opts = dict(max_iter=args.batch_max_iter, tol=1e-6)
+
+    def make(b):
+        w = gen.batched_instance(b)
+        X = torch.tensor(w.X, dtype=torch.float32, device="cuda")
+        e, wt, _ = cc.build_knn_weights(X, None, k=w.k, phi=w.phi)
+        return cc.Problem(X, None, e, wt, precision="mixed"), [float(g) for g in w.gammas]
+
+    N = args.batch_instances
+    inst = [make(b) for b in range(N)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt = cc.Batch([p for p, _ in inst], [g for _, g in inst], autotune=True, **opts)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    cfg = bt.config()
+    t0 = time.perf_counter()
+    _, infos, lat = bt.run(labels=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    solves = sum(len(g) for _, g in inst)
+    print(f"[bench] batched: {N} instances, {solves} solves in {wall:.2f}s", file=sys.stderr, flush=True)
+    bt.close()
+    for p, _ in inst:
+        p.close()
+    times, psolves = [], 0
+    for b in range(min(args.plain_sample, N)):
+        p, g = make(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.solve_path(g, labels=True, **opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        psolves += len(g)
+        p.close()
+    mean_path = float(np.mean(times))
+    fifo = mean_path * np.arange(1, N + 1)  # all N arriving together, one after another
+    return {
+        "instances": N, "solves": solves, "max_iter_per_gamma": args.batch_max_iter,
+        "autotuned": {"vec": cfg["vec"], "items_per_wave": cfg["items_per_wave"],
+                      "us_per_iteration": [round(t, 1) for t in cfg["tune_us"]], "tune_s": round(tune_s, 3)},
+        "solves_per_s": solves / wall, "wall_s": wall,
+        "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99), "max": float(np.max(lat))},
+        "mm_iterations": int(sum(i["iters"] for inf in infos for i in inf)),
+        "plain": {"sample": len(times), "solves_per_s": psolves / sum(times), "mean_path_s": mean_path,
+                  "fifo_latency_ms_estimated": {"p50": 1e3 * _pct(fifo, 50), "p99": 1e3 * _pct(fifo, 99)}},
+    }
+
+
+def bench_served(args):
+    """Requests at their arrival times: the continuous-batching server against
+    the plain path solving them first come, first served."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1409_2065_amd as cc
+    N = args.serve_requests
+    opts = dict(max_iter=args.serve_max_iter, tol=1e-6)
+    arr = gen.served_arrivals(200.0, N)
+    reqs = [gen.served_instance(r) for r in range(N)]
+    solves = sum(len(w.gammas) for w in reqs)
+    torch.cuda.synchronize()
+    srv = cc.Server("mixed", hbm_budget=64 << 30, max_active=256, round_iters=32, **opts)
+    t0 = time.perf_counter()
+    tickets, nxt = {}, 0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < N and arr[nxt] <= now:
+            w = reqs[nxt]
+            tickets[nxt] = srv.submit(w.X, w.mask, k=w.k, phi=w.phi, gammas=w.gammas)
+            nxt += 1
+        a, wt, _ = srv.step()
+        if nxt == N and a == 0 and wt == 0:
+            break
+        if a == 0 and wt == 0:
+            time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
+    wall = time.perf_counter() - t0
+    lat = [srv.status(tickets[r])["t_done"] - srv.status(tickets[r])["t_submit"] for r in range(N)]
+    srv.close()
+    print(f"[bench] served: {N} requests in {wall:.2f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    lat2 = []
+    for r, w in enumerate(reqs):
+        now = time.perf_counter() - t0
+        if now < arr[r]:
+            time.sleep(arr[r] - now)
+        X = torch.tensor(np.nan_to_num(w.X), dtype=torch.float32, device="cuda")
+        M = torch.tensor(w.mask.astype(np.uint8), device="cuda")
+        e, wt, _ = cc.build_knn_weights(X, M, k=w.k, phi=w.phi)
+        with cc.Problem(X, M, e, wt, precision="mixed") as pr:
+            pr.solve_path([float(g) for g in w.gammas], labels=True, **opts)
+        torch.cuda.synchronize()
+        lat2.append(time.perf_counter() - t0 - arr[r])
+    wall2 = time.perf_counter() - t0
+    print(f"[bench] served, plain path: {wall2:.2f}s", file=sys.stderr, flush=True)
+    return {
+        "requests": N, "arrival_rate_per_s": 200.0, "solves": solves, "max_iter_per_gamma": args.serve_max_iter,
+        "server": {"solves_per_s": solves / wall, "requests_per_s": N / wall,
+                   "latency_s": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)}},
+        "plain_fifo": {"solves_per_s": solves / wall2, "requests_per_s": N / wall2,
+                       "latency_s": {"p50": _pct(lat2, 50), "p99": _pct(lat2, 99)}},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "f32", "f64"])
     ap.add_argument("--workload", default="expression", choices=["expression", "genotype", "plain"],
@@ -107,6 +240,13 @@ def main():
     ap.add_argument("--sample-every", type=int, default=8, help="kernel timing sample period")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--batch-max-iter", type=int, default=1000)
+    ap.add_argument("--plain-sample", type=int, default=8)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-max-iter", type=int, default=1000)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -170,7 +310,7 @@ def main():
     achieved = bytes_launch / (pt_ms * 1e-3) / 1e9 if pt_ms > 0 else 0.0
     iter_ms = sum(v["avg_ms"] for v in ks.values())
     result = {
-        "metric": f"pair-feature updates/s (n={n},p={p})",
+        "metric": METRIC if args.workload == "expression" else f"pair-feature updates/s (n={n},p={p})",
         "value": value,
         "unit": "pair-feature updates/s",
         "n_gpus": 1,
@@ -205,9 +345,13 @@ def main():
             "bytes_per_point_feature": per_pf,
         },
     }
+    prob.close()
+    if not args.no_batched:
+        result["batched"] = bench_batched(args)
+    if not args.no_served:
+        result["served"] = bench_served(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-    prob.close()
     print(json.dumps(result), flush=True)
 
 
