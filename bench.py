@@ -38,6 +38,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -70,6 +71,86 @@ def point_sweep_bytes(n, p, E, precision, has_mask):
     if precision == "mixed":
         per_pf += 4 + 4
     return n * p * per_pf + 40 * E, per_pf
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_k_point_expression_n2000_p500_mixed.md")
+KERNEL_SOURCES = ("paper_1409_2065_amd/csrc/solver.hip", "paper_1409_2065_amd/csrc/ccmi_internal.h")
+
+
+def kernel_source_hash():
+    """SHA-256 over the sources the sweep kernels are compiled from; a stored
+    counter reading is used only while this matches the one it was taken with."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload, precision):
+    """HBM bytes per k_point launch from the committed counter summary (two
+    rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, each scaled by what the
+    same counter reads for a device copy of known size), or None when there is
+    none for this workload or the kernel sources changed since it was taken."""
+    if workload != "expression" or precision != "mixed" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["fetch_kib_per_launch"] * rec["fetch_factor"] * 1024 + \
+        rec["write_kib_per_launch"] * rec["write_factor"] * 1024
+
+
+def pmc_summary(fetch_csv, write_csv, copy_mib, command):
+    """Markdown summary of two rocprofv3 counter-collection CSVs (one pass
+    with FETCH_SIZE, one with WRITE_SIZE): per-kernel mean KiB per dispatch,
+    the copy calibration factors, and a JSON record for the k_point kernel."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        vals = defaultdict(list)
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") == counter:
+                    vals[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return vals
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    known_kib = copy_mib * 1024.0
+    copy_f = max(v for k, vs in fetch.items() if "copyBuffer" in k for v in vs)
+    copy_w = max(v for k, vs in write.items() if "copyBuffer" in k for v in vs)
+    ff, wf = known_kib / copy_f, known_kib / copy_w
+    kp = [k for k in fetch if "k_point" in k]
+    if len(kp) != 1:
+        raise SystemExit(f"expected one k_point kernel in the counters, found {kp}")
+    kp = kp[0]
+    fk = sum(fetch[kp]) / len(fetch[kp])
+    wk = sum(write[kp]) / len(write[kp])
+    rec = {"kernel": kp, "source_sha256": kernel_source_hash(), "dispatches": len(fetch[kp]),
+           "fetch_kib_per_launch": round(fk, 3), "write_kib_per_launch": round(wk, 3),
+           "copy_mib": copy_mib, "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+           "fetch_factor": round(ff, 6), "write_factor": round(wf, 6)}
+    out = [f"command (pass 1): `{command.format(counter='FETCH_SIZE')}`",
+           f"command (pass 2): `{command.format(counter='WRITE_SIZE')}`", "",
+           f"Calibration: a device copy of {copy_mib} MiB ({known_kib:.0f} KiB each way) read "
+           f"FETCH_SIZE {copy_f:.0f} KiB and WRITE_SIZE {copy_w:.0f} KiB: factors {ff:.4f} and {wf:.4f}.", "",
+           "| kernel | dispatches | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled MB/dispatch |",
+           "|---|---:|---:|---:|---:|"]
+    for k in sorted(fetch, key=lambda k: -sum(fetch[k])):
+        f_ = sum(fetch[k]) / len(fetch[k])
+        w_ = sum(write.get(k, [0.0])) / max(len(write.get(k, [])), 1)
+        name = k.replace("|", "/")
+        name = name if len(name) <= 60 else name[:57] + "..."
+        out.append(f"| `{name}` | {len(fetch[k])} | {f_:.1f} | {w_:.1f} | {(f_ * ff + w_ * wf) * 1024 / 1e6:.3f} |")
+    out += ["", "```json", json.dumps(rec, indent=1), "```"]
+    print("\n".join(out))
 
 
 def cpu_baseline(wl, seconds):
@@ -247,7 +328,15 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-max-iter", type=int, default=1000)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 counter CSVs (no GPU) and exit")
+    ap.add_argument("--pmc-command", default="", help="command text recorded in the summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.calibrate_copy_mib, args.pmc_command)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -263,6 +352,14 @@ def main():
 
     cc.load()
     dev = torch.device("cuda:0")
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copied {args.calibrate_copy_mib} MiB for counter calibration", file=sys.stderr, flush=True)
     wl = gen.make(args.workload)
     n, p = wl.n, wl.p
     X = torch.tensor(np.nan_to_num(wl.X), dtype=torch.float32, device=dev)
@@ -340,7 +437,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": stored_traffic(args.workload, args.precision),
             "bytes_per_launch": bytes_launch,
             "bytes_per_point_feature": per_pf,
         },

@@ -128,6 +128,7 @@ struct Problem {
   int prof_every = 0;
   int64_t prof_iter = 0;
   std::vector<hipEvent_t> prof_events;  // 4 per sampled iteration
+  hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};  // events of the launch being enqueued
   size_t prof_used = 0;                 // event sets recorded, not yet harvested
   double prof_ms[3] = {0, 0, 0};
   int64_t prof_n[3] = {0, 0, 0};

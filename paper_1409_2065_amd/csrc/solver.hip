@@ -36,6 +36,7 @@
 // tile-major per XCD so that each XCD's L2 holds the rows of the tiles it
 // sweeps.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -500,13 +501,20 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   // previous iteration is finished, so they overlap that reduction.
   // With PF, every item's such loads are issued while the previous item
   // gathers (a wave with several items then waits on one chain per item).
+  // Without a mask the U row is read only in the first iteration of a solve
+  // (afterwards U_m depends on X and A_{m-1} alone).
   const int first = it0 + wave;
   uint32_t mr0 = 0xffffffffu;
   int jl0 = -1;
   double ql0 = 0.0;
   TS up0[VEC];
   TX x0[VEC];
-  auto preload = [&](int item) {
+  auto u_row = [&](int item, TS (&u)[VEC]) {
+    const int t = item / a.n, i = item - t * a.n;
+    const int f0 = t * W + lane * VEC;
+    RawIO<TS, VEC>::load(U + (size_t)i * a.ld + (f0 < a.ld ? f0 : 0), u);
+  };
+  auto preload = [&](int item, bool needU) {
     const int t = item / a.n, i = item - t * a.n;
     const int f0 = t * W + lane * VEC;
     const size_t rowc = (size_t)i * a.ld + (f0 < a.ld ? f0 : 0);
@@ -518,14 +526,21 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
       jl0 = a.colE[i * a.ell_s + lane];
       ql0 = a.qE[i * a.ell_s + lane];  // unused in the first iteration of a solve
     }
-    RawIO<TS, VEC>::load(U + rowc, up0);
+    if (needU) {
+      RawIO<TS, VEC>::load(U + rowc, up0);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) up0[v] = (TS)0;
+    }
     RawIO<TX, VEC>::load(X + rowc, x0);
   };
-  if (first < it1) preload(first);
+  if (first < it1) preload(first, a.M != nullptr);
 
   const DevScalars hs = begin_iteration<kPointWaves, BATCH>(a, red, blk);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
+  const bool needU = a.M != nullptr || m == 0;
+  if (!a.M && m == 0 && first < it1) u_row(first, up0);
   const double rho = hs.rho, dprev = hs.d_prev;
   const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
   // stop-test window: U snapshots at m = 0, K, 2K, ...; A snapshots at
@@ -569,14 +584,14 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
         jl = a.colE[rs + lane];
         if (m > 0) ql = a.qE[rs + lane];
       }
-      RawIO<TS, VEC>::load(U + rowc, upr);
+      if (needU) u_row(item, upr);
       RawIO<TX, VEC>::load(X + rowc, xr);
     }
     TG gr[VEC];
     TS apr[VEC];
     RawIO<TG, VEC>::load(Gp + rowc, gr);
     RawIO<TS, VEC>::load(Ap + rowc, apr);
-    if (PF && item + kPointWaves < it1) preload(item + kPointWaves);
+    if (PF && item + kPointWaves < it1) preload(item + kPointWaves, needU);
     double sumg[VEC], sumcg[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) sumg[v] = sumcg[v] = 0.0;
@@ -1520,18 +1535,31 @@ static Launch sweep_grid(int64_t nitems, int waves = kWavesPerBlock, int ipw = 1
   return L;
 }
 
-// Event set for a sampled iteration (cc_profile), or null.
+// Event set for a sampled iteration (cc_profile), or null: start and end of
+// the point sweep, then of the edge stage.
 static hipEvent_t *prof_slot(Problem *P) {
   if (P->prof_every <= 0) return nullptr;
   const bool sample = (P->prof_iter++ % P->prof_every) == 0;
   if (!sample) return nullptr;
-  const size_t need = 3 * (P->prof_used + 1);
+  const size_t need = 4 * (P->prof_used + 1);
   while (P->prof_events.size() < need) {
     hipEvent_t ev;
     if (hipEventCreate(&ev) != hipSuccess) return nullptr;
     P->prof_events.push_back(ev);
   }
-  return &P->prof_events[3 * P->prof_used++];
+  return &P->prof_events[4 * P->prof_used++];
+}
+
+// Launch on a stream.  With events given, hipExtLaunchKernel stamps them with
+// the kernel's own start (e0) and end (e1), so a sampled duration is the
+// kernel's execution, not the gap between two markers around it.
+template <typename... KArgs, typename... Args>
+static void klaunch(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t stream,
+                    hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, stream, e0, e1, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, args...);
 }
 
 // Arguments of a point sweep: it reads the current scalar slot and writes the
@@ -1547,11 +1575,11 @@ template <int PREC, int VEC>
 static void launch_point_t(Problem *P, const Launch &Lp) {
   // prefetching pays when a wave has more than one item
   if (Lp.chunk > kPointWaves)
-    hipLaunchKernelGGL((k_point<PREC, VEC, true>), dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream,
-                       point_args(P, Lp));
+    klaunch(k_point<PREC, VEC, true>, dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream, P->pev[0], P->pev[1],
+            point_args(P, Lp));
   else
-    hipLaunchKernelGGL((k_point<PREC, VEC, false>), dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream,
-                       point_args(P, Lp));
+    klaunch(k_point<PREC, VEC, false>, dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream, P->pev[0], P->pev[1],
+            point_args(P, Lp));
 }
 
 static EdgeState edge_state(Problem *P) {
@@ -1609,11 +1637,11 @@ static void launch_edge_p(Problem *P, int init, int nbp) {
     const Launch Li = edge_items_grid(P->n_items, P->ipw);
     const EdgeArgs ea = edge_args(P, Li, init, nbp);
     switch (P->item_nv) {
-      case 1: hipLaunchKernelGGL((k_edge_items<PREC, 1>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      case 2: hipLaunchKernelGGL((k_edge_items<PREC, 2>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      case 4: hipLaunchKernelGGL((k_edge_items<PREC, 4>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      case 8: hipLaunchKernelGGL((k_edge_items<PREC, 8>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      default: hipLaunchKernelGGL((k_edge_items<PREC, 16>), dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      case 1: klaunch(k_edge_items<PREC, 1>, dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
+      case 2: klaunch(k_edge_items<PREC, 2>, dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
+      case 4: klaunch(k_edge_items<PREC, 4>, dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
+      case 8: klaunch(k_edge_items<PREC, 8>, dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
+      default: klaunch(k_edge_items<PREC, 16>, dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
     }
     return;
   }
@@ -1621,11 +1649,11 @@ static void launch_edge_p(Problem *P, int init, int nbp) {
     const Launch Le = edge_fused_grid(P->E);
     const EdgeArgs ea = edge_args(P, Le, init, nbp);
     switch (P->npass) {
-      case 1: hipLaunchKernelGGL((k_edge_fused<PREC, 1>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      case 2: hipLaunchKernelGGL((k_edge_fused<PREC, 2>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      case 4: hipLaunchKernelGGL((k_edge_fused<PREC, 4>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      case 8: hipLaunchKernelGGL((k_edge_fused<PREC, 8>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
-      default: hipLaunchKernelGGL((k_edge_fused<PREC, 16>), dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, ea); break;
+      case 1: klaunch(k_edge_fused<PREC, 1>, dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
+      case 2: klaunch(k_edge_fused<PREC, 2>, dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
+      case 4: klaunch(k_edge_fused<PREC, 4>, dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
+      case 8: klaunch(k_edge_fused<PREC, 8>, dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
+      default: klaunch(k_edge_fused<PREC, 16>, dim3(Le.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
     }
     return;
   }
@@ -1634,26 +1662,26 @@ static void launch_edge_p(Problem *P, int init, int nbp) {
     const EdgeArgs ea = edge_args(P, Ls, init, nbp);
     const size_t lds = (size_t)P->n * P->edge_f * sizeof(typename Traits<PREC>::TG);
     switch (P->edge_f) {
-      case 4: hipLaunchKernelGGL((k_edge_slab<PREC, 4>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
-      case 8: hipLaunchKernelGGL((k_edge_slab<PREC, 8>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
-      case 16: hipLaunchKernelGGL((k_edge_slab<PREC, 16>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
-      default: hipLaunchKernelGGL((k_edge_slab<PREC, 32>), dim3(P->entile), dim3(1024), lds, P->stream, ea, P->eslab_tpg, P->eslab_ntf); break;
+      case 4: klaunch(k_edge_slab<PREC, 4>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
+      case 8: klaunch(k_edge_slab<PREC, 8>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
+      case 16: klaunch(k_edge_slab<PREC, 16>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
+      default: klaunch(k_edge_slab<PREC, 32>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
     }
   } else {
     const Launch Le = sweep_grid(P->n * P->entile);
-    hipLaunchKernelGGL((k_edge_tiles<PREC>), dim3(Le.blocks), dim3(kBlock), 0, P->stream,
-                       edge_args(P, Le, init, nbp));
+    klaunch(k_edge_tiles<PREC>, dim3(Le.blocks), dim3(kBlock), 0, P->stream, P->pev[2], nullptr,
+            edge_args(P, Le, init, nbp));
   }
   const int rblocks = edge_reduce_blocks(P->E);
   ReduceArgs ra{P->entile, nbp, init, P->part, edge_state(P), P->esum, P->psum, P->sc + P->slot};
-  hipLaunchKernelGGL(k_edge_reduce, dim3(rblocks), dim3(kEdgeBlock), 0, P->stream, ra);
+  klaunch(k_edge_reduce, dim3(rblocks), dim3(kEdgeBlock), 0, P->stream, nullptr, P->pev[3], ra);
 }
 
 template <int PREC, int F>
 static void launch_point_slab_t(Problem *P, int blocks) {
   const PointArgs pa = point_args(P, Launch{blocks, 0, 0});
   const size_t lds = (size_t)P->n * F * sizeof(typename Traits<PREC>::TG);
-  hipLaunchKernelGGL((k_point_slab<PREC, F>), dim3(blocks), dim3(kBlock), lds, P->stream, pa);
+  klaunch(k_point_slab<PREC, F>, dim3(blocks), dim3(kBlock), lds, P->stream, P->pev[0], P->pev[1], pa);
 }
 
 template <int PREC>
@@ -1697,18 +1725,17 @@ static void launch_point_p(Problem *P, const Launch &Lp) {
 // iteration) and the edge stage.  Advances the host's scalar slot.
 static void launch_iteration(Problem *P) {
   hipEvent_t *ev = prof_slot(P);
-  if (ev) (void)hipEventRecord(ev[0], P->stream);
+  for (int q = 0; q < 4; ++q) P->pev[q] = ev ? ev[q] : nullptr;
   const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves, P->ipw);
   const int nbp = point_blocks(P);
   if (P->precision == kF32) launch_point_p<kF32>(P, Lp);
   else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
   else launch_point_p<kMixed>(P, Lp);
   P->slot ^= 1;
-  if (ev) (void)hipEventRecord(ev[1], P->stream);
   if (P->precision == kF32) launch_edge_p<kF32>(P, 0, nbp);
   else if (P->precision == kF64) launch_edge_p<kF64>(P, 0, nbp);
   else launch_edge_p<kMixed>(P, 0, nbp);
-  if (ev) (void)hipEventRecord(ev[2], P->stream);
+  for (int q = 0; q < 4; ++q) P->pev[q] = nullptr;
 }
 
 // Edge norms of the A in buffer pa (state set or reset).
@@ -1731,10 +1758,10 @@ cc_status profile(Problem *P, int32_t sample_every) {
 // caller has synchronised the stream, so every event is complete.
 cc_status harvest_profile(Problem *P) {
   for (size_t k = 0; k < P->prof_used; ++k) {
-    hipEvent_t *ev = &P->prof_events[3 * k];
+    hipEvent_t *ev = &P->prof_events[4 * k];
     for (int q = 0; q < 2; ++q) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[q], ev[q + 1]) == hipSuccess) {
+      if (hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]) == hipSuccess) {
         P->prof_ms[q] += ms;
         P->prof_n[q] += 1;
       }
@@ -1805,6 +1832,10 @@ static void choose_tiles(Problem *P) {
   if (env) vec = atoi(env);
   if (vec != 1 && vec != 2 && vec != 4) vec = P->p > 256 ? 4 : (P->p > 96 ? 2 : 1);
   P->vec = vec;
+  // items per wave of the point and item edge sweeps (CCMI_IPW = 1, 2 or 4)
+  const char *ei = getenv("CCMI_IPW");
+  const int ipw = ei ? atoi(ei) : 1;
+  P->ipw = (ipw == 2 || ipw == 4) ? ipw : 1;
   P->tile_w = slab > 0 ? slab : kWave * vec;
   P->ntile = (int)cdiv(P->ld, P->tile_w);
   // edge sweep: work items of edges sharing a lower end when the whole row
