@@ -61,13 +61,14 @@ WORKLOAD_TEXT = {
 def point_sweep_bytes(n, p, E, precision, has_mask):
     """Algorithmic bytes of one point-sweep launch: every array element it
     must touch counted once (neighbour rows are re-reads of the same array).
-    Per point-feature: X, mask, U read+write, A' read, A write, and for the
-    mixed precision the FP32 copy of A' read and of A written.  Per edge:
-    the CSR entries of both directions (16 B), the previous norm, the weight
-    and the written shrink factor (8 B each)."""
+    Per point-feature: X, mask, U write (and U read where entries are
+    missing: without a mask U_m follows from X and A_{m-1}), A' read, A
+    write, and for the mixed precision the FP32 copy of A' read and of A
+    written.  Per edge: the neighbour slots of both directions (16 B), the
+    previous norm, the weight and the written shrink factor (8 B each)."""
     sx = 8 if precision == "f64" else 4
     ss = 4 if precision == "f32" else 8
-    per_pf = sx + (1 if has_mask else 0) + 2 * ss + ss + ss
+    per_pf = sx + (1 + ss if has_mask else 0) + ss + ss + ss
     if precision == "mixed":
         per_pf += 4 + 4
     return n * p * per_pf + 40 * E, per_pf

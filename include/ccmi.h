@@ -383,6 +383,66 @@ cc_status cc_server_result(cc_server_t server, int64_t ticket, int32_t *labels,
 cc_status cc_server_release(cc_server_t server, int64_t ticket);
 cc_status cc_server_destroy(cc_server_t server);
 
+/* ---------------------------------------------------------------------
+ * Extras the paper suggests around the solver
+ * ---------------------------------------------------------------------
+ * cc_pca: principal components of the original data, for viewing the
+ * cluster path on them (Evaluation of Clusters).  X (device, x_dtype, n
+ * rows of ldx) and mask (device, may be NULL) as for cc_problem_create;
+ * missing entries are replaced by their observed column means and the
+ * columns centred by those means.  Returns the top r right singular vectors
+ * of the centred matrix, V (device FP64, p x r row-major: V[f * r + c]),
+ * each signed so that its entry of largest magnitude is positive; the
+ * singular values sval (host FP64, r, decreasing); center (device FP64, p,
+ * may be NULL) the column means.  Subspace iteration with r + 8 columns for
+ * iters steps (0 = 100), then a Rayleigh-Ritz step; the accuracy of column
+ * c improves as (sigma_{r+9} / sigma_c)^(2 iters).  1 <= r <= min(16, n, p).
+ *
+ * cc_solve_path_pc: cc_solve_path, except that instead of U the path
+ * returns its projection on the device (Discussion: project before any
+ * transfer): proj (device FP64, n_gamma x n x r), proj[g][i][c] =
+ * sum_f (u_if - center_f) V[f][c] for the U reported at gamma g.  V (device
+ * FP64, p x r as cc_pca writes it), center (device FP64, p, may be NULL =
+ * zero), 1 <= r <= 16.  labels and infos as for cc_solve_path.
+ *
+ * cc_min_connected_k: the smallest k <= k_max for which the kNN graph of
+ * cc_build_knn_weights (same neighbours, ties and imputation) is connected,
+ * found by bisection over k with a connected-components search per step
+ * (Results, "Impact of the Constants k and phi"); -1 when it is not
+ * connected at k_max.  n_components: components at k_max (host output).
+ * 1 <= k_max < n, k_max <= 1024, n <= 16384.
+ *
+ * cc_composite_weights: weights w_e = exp(-phi d_e^2) over given edges
+ * (device ei, ej, n_edges) from the composite distance of eq
+ * composite_distance, d_ij = alpha ||x_i - x_j|| + (1 - alpha) dist(y_i, y_j)
+ * with X (device, x_dtype, n rows of ldx, p columns, no missing entries:
+ * impute first; p may be 0) and coordinates Y (device FP64, n rows of ldy,
+ * q <= 8 columns).  dist is Euclidean over the coordinates, a coordinate
+ * with period[t] > 0 (host, q entries, may be NULL) taken modulo that period
+ * (the shorter way round); geodesic != 0 needs q = 2 and takes (latitude,
+ * longitude) in degrees, dist = radius (<= 0 means 1) times the
+ * great-circle angle.  phi, normalize and phi_used as for
+ * cc_build_knn_weights; w: device output, n_edges.  The result goes to
+ * cc_problem_create as the edge weights. */
+cc_status cc_pca(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
+                 const uint8_t *mask, int64_t ldm, int32_t r, int32_t iters,
+                 double *V, double *sval, double *center, void *stream);
+cc_status cc_solve_path_pc(cc_problem_t prob, int32_t n_gamma, const double *gammas,
+                           const cc_solve_opts *opts, int32_t *labels, int32_t r,
+                           const double *V, const double *center, double *proj,
+                           cc_solve_info *infos);
+cc_status cc_min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *X,
+                             int64_t ldx, const uint8_t *mask, int64_t ldm,
+                             int32_t k_max, int32_t *k_min, int32_t *n_components,
+                             void *stream);
+cc_status cc_composite_weights(int64_t n, int64_t n_edges, const int32_t *ei,
+                               const int32_t *ej, int64_t p, int32_t x_dtype,
+                               const void *X, int64_t ldx, int32_t q,
+                               const double *Y, int64_t ldy, const double *period,
+                               int32_t geodesic, double radius, double alpha,
+                               double phi, int32_t normalize, double *w,
+                               double *phi_used, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,9 @@ that takes torch device tensors.  Build with
 ``python -m paper_1409_2065_amd.build``.
 """
 from ._lib import CCError, LIB_PATH, load  # noqa: F401
-from .api import PRECISIONS, Batch, Problem, Server, build_knn_weights, components, standardize_columns  # noqa: F401
+from .api import (PRECISIONS, Batch, Problem, Server, build_knn_weights, components,  # noqa: F401
+                  composite_weights, min_connected_k, pca, standardize_columns)
 
-__all__ = ["Problem", "Batch", "Server", "build_knn_weights", "standardize_columns", "components", "CCError",
+__all__ = ["Problem", "Batch", "Server", "build_knn_weights", "standardize_columns", "components", "pca",
+           "min_connected_k", "composite_weights", "CCError",
            "PRECISIONS", "load", "LIB_PATH"]

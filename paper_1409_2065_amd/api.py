@@ -117,6 +117,27 @@ class Problem:
                                         _ptr(lab), _ptr(up), infos))
         return [infos[k].as_dict() for k in range(G)], lab, up
 
+    def solve_path_pc(self, gammas: Sequence[float], V, center=None, labels: bool = True, **opts):
+        """cc_solve_path_pc: the path with each gamma's U projected on the
+        device onto the columns of V (p, r): returns (infos, labels,
+        proj (G, n, r) float64)."""
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+        G = g.size
+        V = _dev(V, torch.float64)
+        if V.dim() != 2 or V.shape[0] != self.p:
+            raise ValueError("V must be (p, r)")
+        r = V.shape[1]
+        c = None if center is None else _dev(center, torch.float64)
+        if c is not None and c.numel() != self.p:
+            raise ValueError("center must have p entries")
+        o = default_opts(**opts)
+        infos = (_lib.SolveInfo * max(G, 1))()
+        lab = torch.empty((G, self.n), dtype=torch.int32, device="cuda") if labels else None
+        proj = torch.empty((G, self.n, r), dtype=torch.float64, device="cuda")
+        check(_lib.load().cc_solve_path_pc(self._h, G, g.ctypes.data_as(_lib.P_f64), C.byref(o),
+                                           _ptr(lab), r, _ptr(V), _ptr(c), _ptr(proj), infos))
+        return [infos[k].as_dict() for k in range(G)], lab, proj
+
     # -- results --
     def U(self, dtype=torch.float32) -> torch.Tensor:
         out = torch.empty((self.n, self.p), dtype=dtype, device="cuda")
@@ -212,6 +233,60 @@ def standardize_columns(X: torch.Tensor, mask=None) -> torch.Tensor:
     check(_lib.load().cc_standardize_columns(n, p, _xdtype(X), _ptr(X), p, _ptr(m), p,
                                              C.c_void_p(_stream())))
     return X
+
+
+def pca(X, mask=None, r: int = 2, iters: int = 100):
+    """cc_pca: (V (p, r) float64 on the device, singular values (r,) numpy,
+    column means (p,) float64 on the device) of the mean-imputed, centred X."""
+    X = _dev(X)
+    n, p = X.shape
+    m = _mask(mask, X.shape)
+    V = torch.empty((p, int(r)), dtype=torch.float64, device="cuda")
+    center = torch.empty(p, dtype=torch.float64, device="cuda")
+    sval = np.zeros(int(r), dtype=np.float64)
+    check(_lib.load().cc_pca(n, p, _xdtype(X), _ptr(X), p, _ptr(m), p, int(r), int(iters), _ptr(V),
+                             sval.ctypes.data_as(_lib.P_f64), _ptr(center), C.c_void_p(_stream())))
+    return V, sval, center
+
+
+def min_connected_k(X, mask=None, k_max: int = 32):
+    """cc_min_connected_k: (smallest k <= k_max with a connected kNN graph,
+    or -1; number of components at k_max)."""
+    X = _dev(X)
+    n, p = X.shape
+    m = _mask(mask, X.shape)
+    kmin, ncomp = C.c_int32(), C.c_int32()
+    check(_lib.load().cc_min_connected_k(n, p, _xdtype(X), _ptr(X), p, _ptr(m), p, int(k_max),
+                                         C.byref(kmin), C.byref(ncomp), C.c_void_p(_stream())))
+    return int(kmin.value), int(ncomp.value)
+
+
+def composite_weights(edges, X, Y, alpha: float, phi: float = -0.5, period=None,
+                      geodesic: bool = False, radius: float = 1.0, normalize: bool = False):
+    """cc_composite_weights: (w (E,) float64 on the device, phi_used) from
+    d = alpha ||x_i - x_j|| + (1 - alpha) dist(y_i, y_j) over the edges."""
+    e = _dev(edges, torch.int32).reshape(-1, 2)
+    ei = e[:, 0].contiguous()
+    ej = e[:, 1].contiguous()
+    X = _dev(X)
+    Y = _dev(Y, torch.float64)
+    if Y.dim() == 1:
+        Y = Y.reshape(-1, 1)
+    n, p = X.shape
+    q = Y.shape[1]
+    if Y.shape[0] != n:
+        raise ValueError("X and Y need the same number of rows")
+    per = None
+    if period is not None:
+        per = np.ascontiguousarray(np.asarray(period, dtype=np.float64).reshape(q))
+    w = torch.empty(e.shape[0], dtype=torch.float64, device="cuda")
+    phi_used = C.c_double()
+    check(_lib.load().cc_composite_weights(
+        n, e.shape[0], _ptr(ei), _ptr(ej), p, _xdtype(X), _ptr(X), p, q, _ptr(Y), q,
+        None if per is None else per.ctypes.data_as(_lib.P_f64), 1 if geodesic else 0, float(radius),
+        float(alpha), float(phi), 1 if normalize else 0, _ptr(w), C.byref(phi_used),
+        C.c_void_p(_stream())))
+    return w, phi_used.value
 
 
 def components(n: int, edges, keep=None):

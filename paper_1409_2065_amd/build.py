@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libccmi.so")
-SOURCES = ["solver.hip", "knn.hip", "api.hip"]
+SOURCES = ["solver.hip", "knn.hip", "extras.hip", "api.hip"]
 ARCH = os.environ.get("CCMI_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

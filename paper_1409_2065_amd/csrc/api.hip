@@ -167,6 +167,38 @@ cc_status cc_solve_path(cc_problem_t prob, int32_t n_gamma, const double *gammas
   CC_GUARD_END
 }
 
+cc_status cc_solve_path_pc(cc_problem_t prob, int32_t n_gamma, const double *gammas,
+                           const cc_solve_opts *opts, int32_t *labels, int32_t r,
+                           const double *V, const double *center, double *proj,
+                           cc_solve_info *infos) {
+  CC_GUARD_BEGIN
+  if (!prob) { set_error("problem is NULL"); return CC_ERR_INVALID_ARG; }
+  if (n_gamma < 0 || (n_gamma > 0 && !gammas)) { set_error("bad gamma array"); return CC_ERR_INVALID_ARG; }
+  if (!opts_ok(opts)) { set_error("opts->struct_size mismatch"); return CC_ERR_INVALID_ARG; }
+  if (r < 1 || r > 16 || !V || !proj) { set_error("need 1 <= r <= 16 and V, proj"); return CC_ERR_INVALID_ARG; }
+  for (int32_t g = 0; g < n_gamma; ++g)
+    if (!(gammas[g] >= 0.0)) { set_error("gammas must be >= 0"); return CC_ERR_INVALID_ARG; }
+  Problem *P = reinterpret_cast<Problem *>(prob);
+  cc_solve_opts o = resolve(opts);
+  for (int32_t g = 0; g < n_gamma; ++g) {
+    cc_solve_info info;
+    std::memset(&info, 0, sizeof(info));
+    cc_status s = solve(P, gammas[g], o, &info);
+    if (infos) infos[g] = info;
+    if (s != CC_OK) return s;
+    if (labels) {
+      s = write_labels(P, labels + (size_t)g * P->n, nullptr);
+      if (s != CC_OK) return s;
+    }
+    s = project_U(P, r, V, center, proj + (size_t)g * P->n * r);
+    if (s != CC_OK) return s;
+    o.warm_start = 1;
+  }
+  if (hipStreamSynchronize(P->stream) != hipSuccess) { set_error("stream sync failed"); return CC_ERR_HIP; }
+  return CC_OK;
+  CC_GUARD_END
+}
+
 cc_status cc_batch_create(int32_t n_inst, const cc_problem_t *problems, const int32_t *n_gamma,
                           const double *gammas, const cc_solve_opts *opts, int32_t autotune,
                           cc_batch_t *out) {
@@ -474,6 +506,34 @@ cc_status cc_standardize_columns(int64_t n, int64_t p, int32_t x_dtype, void *X,
                                  const uint8_t *mask, int64_t ldm, void *stream) {
   CC_GUARD_BEGIN
   return standardize_columns(n, p, x_dtype, X, ldx, mask, ldm, (hipStream_t)stream);
+  CC_GUARD_END
+}
+
+cc_status cc_pca(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
+                 const uint8_t *mask, int64_t ldm, int32_t r, int32_t iters, double *V,
+                 double *sval, double *center, void *stream) {
+  CC_GUARD_BEGIN
+  return pca(n, p, x_dtype, X, ldx, mask, ldm, r, iters, V, sval, center, (hipStream_t)stream);
+  CC_GUARD_END
+}
+
+cc_status cc_min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
+                             const uint8_t *mask, int64_t ldm, int32_t k_max, int32_t *k_min,
+                             int32_t *n_components, void *stream) {
+  CC_GUARD_BEGIN
+  return min_connected_k(n, p, x_dtype, X, ldx, mask, ldm, k_max, k_min, n_components,
+                         (hipStream_t)stream);
+  CC_GUARD_END
+}
+
+cc_status cc_composite_weights(int64_t n, int64_t n_edges, const int32_t *ei, const int32_t *ej,
+                               int64_t p, int32_t x_dtype, const void *X, int64_t ldx, int32_t q,
+                               const double *Y, int64_t ldy, const double *period,
+                               int32_t geodesic, double radius, double alpha, double phi,
+                               int32_t normalize, double *w, double *phi_used, void *stream) {
+  CC_GUARD_BEGIN
+  return composite_weights(n, n_edges, ei, ej, p, x_dtype, X, ldx, q, Y, ldy, period, geodesic,
+                           radius, alpha, phi, normalize, w, phi_used, (hipStream_t)stream);
   CC_GUARD_END
 }
 

@@ -284,5 +284,23 @@ cc_status build_knn_weights(int64_t n, int64_t p, int32_t x_dtype,
 cc_status standardize_columns(int64_t n, int64_t p, int32_t x_dtype, void *X,
                               int64_t ldx, const uint8_t *mask, int64_t ldm,
                               hipStream_t stream);
+cc_status min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *X,
+                          int64_t ldx, const uint8_t *mask, int64_t ldm,
+                          int32_t k_max, int32_t *k_min, int32_t *n_components,
+                          hipStream_t stream);
+cc_status composite_weights(int64_t n, int64_t n_edges, const int32_t *ei,
+                            const int32_t *ej, int64_t p, int32_t x_dtype,
+                            const void *X, int64_t ldx, int32_t q,
+                            const double *Y, int64_t ldy, const double *period,
+                            int32_t geodesic, double radius, double alpha,
+                            double phi, int32_t normalize, double *w,
+                            double *phi_used, hipStream_t stream);
+
+// ---- principal components and path projection (extras.hip) ----
+cc_status pca(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
+              const uint8_t *mask, int64_t ldm, int32_t r, int32_t iters,
+              double *V, double *sval, double *center, hipStream_t stream);
+cc_status project_U(Problem *P, int32_t r, const double *V, const double *center,
+                    double *out);
 
 }  // namespace ccmi

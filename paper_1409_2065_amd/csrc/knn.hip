@@ -13,6 +13,11 @@
 //      prefix-summed per row, written out as sorted edges (i < j);
 //   6. exact FP64 d2 per edge, phi (literal or |phi| / lower median d2),
 //      w = exp(-phi d2), optional normalisation to sum 1.
+//
+// Also here: the smallest k whose kNN graph is connected (Results, "Impact
+// of the Constants k and phi": bisection over k with a graph search), and
+// weights from the composite distance of genotypes and coordinates
+// (composite_distance).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -347,6 +352,74 @@ __global__ void k_phi_from_median(const double *med, double c, double *phi) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *phi = (*med > 0.0) ? c / *med : 0.0;
 }
 
+// ------------------------------------------------ connectivity over k
+// Directed pairs (i, q-th neighbour of i) of the k_max lists.
+__global__ void k_knn_pairs(int n, int kmax, const int32_t *knn, int32_t *ei, int32_t *ej) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (int64_t)n * kmax) {
+    ei[e] = (int32_t)(e / kmax);
+    ej[e] = knn[e];
+  }
+}
+
+// Keep the pairs of the first k neighbours: the union graph of i ~_k j.
+__global__ void k_keep_prefix(int64_t m, int kmax, int k, uint8_t *keep) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) keep[e] = (e % kmax) < k ? 1 : 0;
+}
+
+// ------------------------------------------------ composite distance
+constexpr int kMaxCoords = 8;
+struct CoordSpec {
+  int q, geodesic;
+  double radius, alpha;
+  double period[kMaxCoords];
+};
+
+// One wave per edge: d = alpha ||x_i - x_j|| + (1 - alpha) dist_y(i, j),
+// written as d^2.  dist_y is Euclidean over the coordinates, each
+// difference taken modulo its period when that is positive, or with
+// geodesic != 0 the great-circle distance of (latitude, longitude) in
+// degrees (haversine form) times the radius.
+template <typename TI>
+__global__ void k_edge_composite(int E, int p, const TI *X, int64_t ldx, const double *Y,
+                                 int64_t ldy, CoordSpec c, const int32_t *ei, const int32_t *ej,
+                                 double *d2) {
+  const int e = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (e >= E) return;
+  const int i = ei[e], j = ej[e];
+  double acc = 0.0;
+  for (int f = lane; f < p; f += kWave) {
+    const double d = (double)X[(size_t)j * ldx + f] - (double)X[(size_t)i * ldx + f];
+    acc = fma(d, d, acc);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  if (lane != 0) return;
+  const double *yi = Y + (size_t)i * ldy, *yj = Y + (size_t)j * ldy;
+  double dy = 0.0;
+  if (c.geodesic) {
+    const double r = 3.14159265358979323846 / 180.0;
+    const double la1 = yi[0] * r, la2 = yj[0] * r, dla = la2 - la1, dlo = (yj[1] - yi[1]) * r;
+    const double sa = sin(0.5 * dla), so = sin(0.5 * dlo);
+    const double h = fmin(fmax(sa * sa + cos(la1) * cos(la2) * so * so, 0.0), 1.0);
+    dy = c.radius * 2.0 * atan2(sqrt(h), sqrt(1.0 - h));
+  } else {
+    double s2 = 0.0;
+    for (int t = 0; t < c.q; ++t) {
+      double d = fabs(yj[t] - yi[t]);
+      if (c.period[t] > 0.0) {
+        d = fmod(d, c.period[t]);
+        d = fmin(d, c.period[t] - d);
+      }
+      s2 = fma(d, d, s2);
+    }
+    dy = sqrt(s2);
+  }
+  const double d = c.alpha * sqrt(acc) + (1.0 - c.alpha) * dy;
+  d2[e] = d * d;
+}
+
 // ====================================================================== host
 struct DevBuf {
   void *p = nullptr;
@@ -369,19 +442,18 @@ struct DevBuf {
     if (_s != CC_OK) return _s; \
   } while (0)
 
+// Steps 1-4: the mean-imputed X~ in FP64 (Xd, n x p) and the k nearest
+// neighbours of every row by (exact d2, index) (knn, n x k).
 template <typename TI>
-static cc_status knn_impl(int64_t n, int64_t p, const TI *X, int64_t ldx, const uint8_t *mask,
-                          int64_t ldm, int32_t k, double phi, int32_t normalize, int32_t *ei,
-                          int32_t *ej, double *w, int64_t capacity, int64_t *n_edges,
-                          double *phi_used, hipStream_t st) {
+static cc_status knn_lists(int64_t n, int64_t p, const TI *X, int64_t ldx, const uint8_t *mask,
+                           int64_t ldm, int32_t k, hipStream_t st, DevBuf &Xd, DevBuf &knn) {
   const int64_t n_pad = cdiv64(n, kGT) * kGT;
   const int64_t ldk = cdiv64(p, kKC) * kKC;
   const int K = (int)std::min<int64_t>(n - 1, (int64_t)k + std::max(16, (int)k));
   int npow2 = 1;
   while (npow2 < n) npow2 <<= 1;
-  const int words = (int)cdiv64(n, 32);
 
-  DevBuf mean, bad, Xf, Xd, nrm, D2, cand, knn, bm, cnt, off, total, d2, med, phid;
+  DevBuf mean, bad, Xf, nrm, D2, cand;
   KN_TRY(mean.alloc(p * 8));
   KN_TRY(bad.alloc(4));
   KN_TRY(Xf.alloc((size_t)n_pad * ldk * 4));
@@ -390,12 +462,6 @@ static cc_status knn_impl(int64_t n, int64_t p, const TI *X, int64_t ldx, const 
   KN_TRY(D2.alloc((size_t)n * n * 4));
   KN_TRY(cand.alloc((size_t)n * K * 4));
   KN_TRY(knn.alloc((size_t)n * k * 4));
-  KN_TRY(bm.alloc((size_t)n * words * 4));
-  KN_TRY(cnt.alloc(n * 4));
-  KN_TRY(off.alloc(n * 4));
-  KN_TRY(total.alloc(8));
-  KN_TRY(med.alloc(8));
-  KN_TRY(phid.alloc(8));
 
   CC_HIP(hipMemsetAsync(bad.p, 0, 4, st));
   hipLaunchKernelGGL((k_col_moments<TI>), dim3((int)cdiv64(p, 256)), dim3(256), 0, st, (int)n,
@@ -421,6 +487,51 @@ static cc_status knn_impl(int64_t n, int64_t p, const TI *X, int64_t ldx, const 
   CC_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_recheck, dim3((int)n), dim3(256), (size_t)K * 12, st, (int)n, (int)p,
                      Xd.as<double>(), K, (int)k, cand.as<int32_t>(), knn.as<int32_t>());
+  CC_HIP(hipGetLastError());
+  return CC_OK;
+}
+
+// Step 6 over E edges with squared distances d2 (device): phi (literal, or
+// |phi| / lower median of d2 when phi < 0), w = exp(-phi d2), optional
+// normalisation to sum 1; phi_used (host, may be NULL) gets phi.
+static cc_status finish_weights(int64_t E, const double *d2, double phi, int32_t normalize,
+                                double *w, double *phi_used, hipStream_t st) {
+  DevBuf med, phid;
+  KN_TRY(med.alloc(8));
+  KN_TRY(phid.alloc(8));
+  double hphi = phi;
+  if (phi < 0.0 && E > 0) {
+    hipLaunchKernelGGL(k_lower_median, dim3(1), dim3(1024), 0, st, (int)E, d2, med.as<double>());
+    hipLaunchKernelGGL(k_phi_from_median, dim3(1), dim3(1), 0, st, med.as<double>(), -phi,
+                       phid.as<double>());
+  } else {
+    if (phi < 0.0) hphi = 0.0;
+    CC_HIP(hipMemcpyAsync(phid.p, &hphi, 8, hipMemcpyHostToDevice, st));
+  }
+  if (E > 0) {
+    hipLaunchKernelGGL(k_weights, dim3((int)cdiv64(E, 256)), dim3(256), 0, st, (int)E, d2,
+                       phid.as<double>(), w);
+    if (normalize) hipLaunchKernelGGL(k_normalize, dim3(1), dim3(1024), 0, st, (int)E, w);
+  }
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipMemcpyAsync(&hphi, phid.p, 8, hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (phi_used) *phi_used = hphi;
+  return CC_OK;
+}
+
+template <typename TI>
+static cc_status knn_impl(int64_t n, int64_t p, const TI *X, int64_t ldx, const uint8_t *mask,
+                          int64_t ldm, int32_t k, double phi, int32_t normalize, int32_t *ei,
+                          int32_t *ej, double *w, int64_t capacity, int64_t *n_edges,
+                          double *phi_used, hipStream_t st) {
+  const int words = (int)cdiv64(n, 32);
+  DevBuf Xd, knn, bm, cnt, off, total, d2;
+  KN_TRY(knn_lists(n, p, X, ldx, mask, ldm, k, st, Xd, knn));
+  KN_TRY(bm.alloc((size_t)n * words * 4));
+  KN_TRY(cnt.alloc(n * 4));
+  KN_TRY(off.alloc(n * 4));
+  KN_TRY(total.alloc(8));
   CC_HIP(hipMemsetAsync(bm.p, 0, (size_t)n * words * 4, st));
   hipLaunchKernelGGL(k_mark_pairs, dim3((int)cdiv64(n * k, 256)), dim3(256), 0, st, (int)n,
                      (int)k, words, knn.as<int32_t>(), bm.as<uint32_t>());
@@ -443,27 +554,120 @@ static cc_status knn_impl(int64_t n, int64_t p, const TI *X, int64_t ldx, const 
     hipLaunchKernelGGL(k_edge_d2, dim3((int)cdiv64(E, 4)), dim3(256), 0, st, (int)E, (int)p,
                        Xd.as<double>(), ei, ej, d2.as<double>());
   }
-  double hphi = phi;
-  if (phi < 0.0 && E > 0) {
-    hipLaunchKernelGGL(k_lower_median, dim3(1), dim3(1024), 0, st, (int)E, d2.as<double>(),
-                       med.as<double>());
-    hipLaunchKernelGGL(k_phi_from_median, dim3(1), dim3(1), 0, st, med.as<double>(), -phi,
-                       phid.as<double>());
-  } else {
-    if (phi < 0.0) hphi = 0.0;
-    CC_HIP(hipMemcpyAsync(phid.p, &hphi, 8, hipMemcpyHostToDevice, st));
-  }
-  if (E > 0) {
-    hipLaunchKernelGGL(k_weights, dim3((int)cdiv64(E, 256)), dim3(256), 0, st, (int)E,
-                       d2.as<double>(), phid.as<double>(), w);
-    if (normalize) hipLaunchKernelGGL(k_normalize, dim3(1), dim3(1024), 0, st, (int)E, w);
-  }
-  CC_HIP(hipGetLastError());
-  CC_HIP(hipMemcpyAsync(&hphi, phid.p, 8, hipMemcpyDeviceToHost, st));
-  CC_HIP(hipStreamSynchronize(st));
   *n_edges = E;
-  if (phi_used) *phi_used = hphi;
+  return finish_weights(E, d2.as<double>(), phi, normalize, w, phi_used, st);
+}
+
+template <typename TI>
+static cc_status min_k_impl(int64_t n, int64_t p, const TI *X, int64_t ldx, const uint8_t *mask,
+                            int64_t ldm, int32_t kmax, int32_t *k_min, int32_t *n_comp,
+                            hipStream_t st) {
+  DevBuf Xd, knn, ei, ej, keep, lab, ncl;
+  KN_TRY(knn_lists(n, p, X, ldx, mask, ldm, kmax, st, Xd, knn));
+  const int64_t m = n * kmax;
+  KN_TRY(ei.alloc(m * 4));
+  KN_TRY(ej.alloc(m * 4));
+  KN_TRY(keep.alloc(m));
+  KN_TRY(lab.alloc(n * 4));
+  KN_TRY(ncl.alloc(4));
+  hipLaunchKernelGGL(k_knn_pairs, dim3((int)cdiv64(m, 256)), dim3(256), 0, st, (int)n, (int)kmax,
+                     knn.as<int32_t>(), ei.as<int32_t>(), ej.as<int32_t>());
+  CC_HIP(hipGetLastError());
+  // components of the union graph of the first k neighbours
+  auto count = [&](int k, int32_t *out) -> cc_status {
+    hipLaunchKernelGGL(k_keep_prefix, dim3((int)cdiv64(m, 256)), dim3(256), 0, st, m, (int)kmax, k,
+                       keep.as<uint8_t>());
+    CC_HIP(hipGetLastError());
+    KN_TRY(components(n, m, ei.as<int32_t>(), ej.as<int32_t>(), keep.as<uint8_t>(), nullptr,
+                      lab.as<int32_t>(), ncl.as<int32_t>(), st));
+    CC_HIP(hipMemcpyAsync(out, ncl.p, 4, hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    return CC_OK;
+  };
+  int32_t c = 0;
+  KN_TRY(count(kmax, &c));
+  *n_comp = c;
+  if (c != 1) {
+    *k_min = -1;
+    return CC_OK;
+  }
+  // the graph for k is a subgraph of the one for k + 1: connectivity is
+  // monotone in k, so bisection finds the smallest connected k
+  int lo = 1, hi = kmax;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo) / 2;
+    KN_TRY(count(mid, &c));
+    if (c == 1) hi = mid;
+    else lo = mid + 1;
+  }
+  *k_min = hi;
   return CC_OK;
+}
+
+cc_status min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
+                          const uint8_t *mask, int64_t ldm, int32_t k_max, int32_t *k_min,
+                          int32_t *n_components, hipStream_t stream) {
+  if (n < 2 || p < 1) { set_error("need n >= 2 and p >= 1"); return CC_ERR_INVALID_ARG; }
+  if (n > 16384) { set_error("cc_min_connected_k supports n <= 16384"); return CC_ERR_INVALID_ARG; }
+  if ((int64_t)n * p > ((int64_t)1 << 31) - 1) { set_error("n * p too large"); return CC_ERR_INVALID_ARG; }
+  if (k_max < 1 || k_max >= n || k_max > 1024) { set_error("need 1 <= k_max < n and k_max <= 1024"); return CC_ERR_INVALID_ARG; }
+  if ((int64_t)n * k_max > ((int64_t)1 << 31) - 1) { set_error("n * k_max too large"); return CC_ERR_INVALID_ARG; }
+  if (!X || !k_min || !n_components) { set_error("NULL argument"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype != CC_DTYPE_F32 && x_dtype != CC_DTYPE_F64) { set_error("bad x_dtype"); return CC_ERR_INVALID_ARG; }
+  if (ldx < p || (mask && ldm < p)) { set_error("leading dimension < p"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype == CC_DTYPE_F32)
+    return min_k_impl<float>(n, p, (const float *)X, ldx, mask, ldm, k_max, k_min, n_components, stream);
+  return min_k_impl<double>(n, p, (const double *)X, ldx, mask, ldm, k_max, k_min, n_components, stream);
+}
+
+cc_status composite_weights(int64_t n, int64_t n_edges, const int32_t *ei, const int32_t *ej,
+                            int64_t p, int32_t x_dtype, const void *X, int64_t ldx, int32_t q,
+                            const double *Y, int64_t ldy, const double *period, int32_t geodesic,
+                            double radius, double alpha, double phi, int32_t normalize, double *w,
+                            double *phi_used, hipStream_t st) {
+  if (n < 1 || p < 0 || n_edges < 0) { set_error("need n >= 1, p >= 0, n_edges >= 0"); return CC_ERR_INVALID_ARG; }
+  if (n_edges > ((int64_t)1 << 31) - 1 || n > ((int64_t)1 << 31) - 1) { set_error("n or n_edges too large"); return CC_ERR_INVALID_ARG; }
+  if (n_edges > 0 && (!ei || !ej || !w)) { set_error("NULL edge or weight array"); return CC_ERR_INVALID_ARG; }
+  if (p > 0 && (!X || ldx < p)) { set_error("X is NULL or ldx < p"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype != CC_DTYPE_F32 && x_dtype != CC_DTYPE_F64) { set_error("bad x_dtype"); return CC_ERR_INVALID_ARG; }
+  if (q < 0 || q > kMaxCoords) { set_error("need 0 <= q <= 8 coordinates"); return CC_ERR_INVALID_ARG; }
+  if (q > 0 && (!Y || ldy < q)) { set_error("Y is NULL or ldy < q"); return CC_ERR_INVALID_ARG; }
+  if (geodesic && q != 2) { set_error("geodesic distances need q = 2 (latitude, longitude in degrees)"); return CC_ERR_INVALID_ARG; }
+  if (!(alpha >= 0.0 && alpha <= 1.0)) { set_error("need 0 <= alpha <= 1"); return CC_ERR_INVALID_ARG; }
+  if (!std::isfinite(phi) || !std::isfinite(radius)) { set_error("phi and radius must be finite"); return CC_ERR_INVALID_ARG; }
+  CoordSpec c{};
+  c.q = q;
+  c.geodesic = geodesic ? 1 : 0;
+  c.radius = radius > 0.0 ? radius : 1.0;
+  c.alpha = alpha;
+  for (int t = 0; t < q; ++t) {
+    c.period[t] = period ? period[t] : 0.0;
+    if (!std::isfinite(c.period[t]) || c.period[t] < 0.0) { set_error("periods must be finite and >= 0"); return CC_ERR_INVALID_ARG; }
+  }
+  if (n_edges > 0) {  // every endpoint in range before any launch reads rows
+    std::vector<int32_t> hi(n_edges), hj(n_edges);
+    CC_HIP(hipMemcpyAsync(hi.data(), ei, n_edges * 4, hipMemcpyDeviceToHost, st));
+    CC_HIP(hipMemcpyAsync(hj.data(), ej, n_edges * 4, hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    for (int64_t e = 0; e < n_edges; ++e)
+      if (hi[e] < 0 || hi[e] >= n || hj[e] < 0 || hj[e] >= n) {
+        set_error("edge endpoint out of range");
+        return CC_ERR_INVALID_ARG;
+      }
+  }
+  DevBuf d2;
+  KN_TRY(d2.alloc(n_edges * 8));
+  if (n_edges > 0) {
+    const int blocks = (int)cdiv64(n_edges, 4);
+    if (x_dtype == CC_DTYPE_F32)
+      hipLaunchKernelGGL((k_edge_composite<float>), dim3(blocks), dim3(256), 0, st, (int)n_edges,
+                         (int)p, (const float *)X, ldx, Y, ldy, c, ei, ej, d2.as<double>());
+    else
+      hipLaunchKernelGGL((k_edge_composite<double>), dim3(blocks), dim3(256), 0, st, (int)n_edges,
+                         (int)p, (const double *)X, ldx, Y, ldy, c, ei, ej, d2.as<double>());
+    CC_HIP(hipGetLastError());
+  }
+  return finish_weights(n_edges, d2.as<double>(), phi, normalize, w, phi_used, st);
 }
 
 cc_status build_knn_weights(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,

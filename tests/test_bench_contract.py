@@ -17,9 +17,40 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in out.stderr
 
 
+# without a mask the point sweep reads U only in a solve's first iteration,
+# so the U read (8 B, or 4 B in f32) is not algorithmic traffic
 @pytest.mark.parametrize("prec,mask,expect", [("mixed", True, 45), ("f32", True, 21),
-                                              ("f64", True, 41), ("mixed", False, 44)])
+                                              ("f64", True, 41), ("mixed", False, 36),
+                                              ("f32", False, 16)])
 def test_point_sweep_bytes(prec, mask, expect):
     b, per_pf = bench.point_sweep_bytes(2000, 500, 22965, prec, mask)
     assert per_pf == expect
     assert b == 2000 * 500 * expect + 40 * 22965
+
+
+def _fake_counters(path, counter, copy_kib, kp_kib):
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writerow([1, "__amd_rocclr_copyBuffer", counter, copy_kib])
+        w.writerow([2, "void ccmi::k_point<1, 4, false>(ccmi::PointArgs)", counter, kp_kib])
+        w.writerow([3, "void ccmi::k_point<1, 4, false>(ccmi::PointArgs)", counter, kp_kib + 2])
+        w.writerow([4, "void ccmi::k_edge_items<1, 8>(ccmi::EdgeArgs)", counter, 7])
+
+
+def test_counter_summary_scales_by_the_copy_and_checks_the_source_hash(tmp_path, capsys, monkeypatch):
+    f, w = tmp_path / "f.csv", tmp_path / "w.csv"
+    _fake_counters(f, "FETCH_SIZE", 131072.0, 1000.0)   # the copy reads half: factor 2
+    _fake_counters(w, "WRITE_SIZE", 262144.0, 500.0)
+    bench.pmc_summary(str(f), str(w), 256, "rocprofv3 --pmc {counter} -- x")
+    text = capsys.readouterr().out
+    assert "factors 2.0000 and 1.0000" in text
+    prof = tmp_path / "traffic.md"
+    prof.write_text(text)
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    got = bench.stored_traffic("expression", "mixed")
+    assert got == pytest.approx((1001.0 * 2.0 + 501.0) * 1024)
+    assert bench.stored_traffic("genotype", "mixed") is None
+    prof.write_text(text.replace(bench.kernel_source_hash(), "0" * 64))
+    assert bench.stored_traffic("expression", "mixed") is None
