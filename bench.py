@@ -31,6 +31,10 @@ names (solves/s and latency, against the plain per-solve path):
            first served by the plain path; each gamma capped at
            --serve-max-iter MM iterations.
 
+  extras   principal components (r = 2), the smallest connected k (k_max =
+           128), composite-distance weights, and the path returned as U
+           against its projection on two principal components.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -310,6 +314,51 @@ def bench_served(args):
     }
 
 
+def bench_extras(X, M, edges, w, gammas, args):
+    """The paper's extras on the headline workload: principal components,
+    the smallest connected k, composite-distance weights, and the 30-gamma
+    path (each gamma capped at --extras-max-iter iterations) returned as U
+    on the host against its projection on two principal components."""
+    import numpy as np
+    import torch
+
+    import paper_1409_2065_amd as cc
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, 1e3 * (time.perf_counter() - t0)
+
+    (V, sval, center), pca_ms = timed(lambda: cc.pca(X, M, r=2, iters=100))
+    (kmin, ncomp), mink_ms = timed(lambda: cc.min_connected_k(X, M, k_max=128))
+    rng = np.random.default_rng(7)
+    n = X.shape[0]
+    Y = torch.tensor(np.stack([rng.uniform(-60, 60, n), rng.uniform(-180, 180, n)], axis=1), device="cuda")
+    Xc = X if M is None else X.clone()
+    if M is not None:  # the composite distance takes complete data: mean-impute
+        mf = M.to(torch.float32)
+        mean = (Xc * mf).sum(0) / mf.sum(0).clamp(min=1)
+        Xc = torch.where(M.bool(), Xc, mean.expand_as(Xc)).contiguous()
+    _, comp_ms = timed(lambda: cc.composite_weights(edges, Xc, Y, 0.5, -0.5, geodesic=True, radius=6371.0))
+    opts = dict(max_iter=args.extras_max_iter, labels=True)
+    with cc.Problem(X, M, edges, w, precision="mixed") as g:
+        (_, _, Up), _ = timed(lambda: g.solve_path(gammas, U_path=True, **opts))
+        g.reset_state()
+        _, u_ms = timed(lambda: (g.solve_path(gammas, U_path=True, **opts)[2].cpu()))
+        g.reset_state()
+        _, pc_ms = timed(lambda: (g.solve_path_pc(gammas, V, center, **opts)[2].cpu()))
+    return {
+        "pca": {"r": 2, "iters": 100, "ms": pca_ms, "singular_values": [float(v) for v in sval]},
+        "min_connected_k": {"k_max": 128, "k_min": kmin, "components_at_k_max": ncomp, "ms": mink_ms},
+        "composite_weights": {"alpha": 0.5, "geodesic": True, "edges": int(edges.shape[0]), "ms": comp_ms},
+        "path_to_host": {"gammas": len(gammas), "max_iter_per_gamma": args.extras_max_iter,
+                         "U_ms": u_ms, "U_bytes": int(Up.numel() * 4),
+                         "projected_ms": pc_ms, "projected_bytes": int(len(gammas) * n * 2 * 8)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -329,6 +378,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-max-iter", type=int, default=1000)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras-max-iter", type=int, default=100)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first copy this many MiB device to device (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -444,6 +495,9 @@ def main():
         },
     }
     prob.close()
+    if not args.no_extras and args.workload == "expression":
+        result["extras"] = bench_extras(X, M, edges, w, gammas, args)
+        print("[bench] extras done", file=sys.stderr, flush=True)
     if not args.no_batched:
         result["batched"] = bench_batched(args)
     if not args.no_served:
