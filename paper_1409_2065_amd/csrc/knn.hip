@@ -109,32 +109,52 @@ __global__ void k_rownorm(int n_pad, int ldk, const float *Xf, float *nrm) {
 // ------------------------------------------------------------ MFMA Gram
 // Output tile 64 x 64 per block of 4 waves; wave w owns rows 16w..16w+15 and
 // all 64 columns as four 16 x 16 accumulators.  K is staged through LDS in
-// chunks of 16 features.  v_mfma_f32_16x16x4_f32 operand layout (wave64):
-// A element (row l%16, k l/16), B element (k l/16, col l%16), and result
-// register r of lane l holds (row 4*(l/16)+r, col l%16).
-constexpr int kGT = 64, kKC = 16;
+// chunks of 32 features; the next chunk's global loads are in flight while
+// the current chunk's MFMAs run.  v_mfma_f32_16x16x4_f32 operand layout
+// (wave64): A element (row l%16, k l/16), B element (k l/16, col l%16), and
+// result register r of lane l holds (row 4*(l/16)+r, col l%16).
+// When the output tiles alone cannot fill the chip, blockIdx.z splits K:
+// each split writes its partial tile to part, and k_gram_combine adds the
+// splits in a fixed order.
+constexpr int kGT = 64, kKC = 32;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_gram_d2(int n, int n_pad, int ldk, const float *Xf,
-                                                 const float *nrm, float *D2, int64_t ldd) {
+__global__ __launch_bounds__(256) void k_gram_d2(int n, int n_pad, int ldk, int nsplit,
+                                                 const float *Xf, const float *nrm, float *D2,
+                                                 int64_t ldd, float *part) {
   __shared__ float As[kGT][kKC + 1];
   __shared__ float Bs[kGT][kKC + 1];
   const int bi = blockIdx.y * kGT, bj = blockIdx.x * kGT;
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  const int nch = ldk / kKC;
+  const int per = (nch + nsplit - 1) / nsplit;
+  const int c0 = blockIdx.z * per, c1 = min(nch, c0 + per);
+  // 64 rows x 32 floats per operand: thread tid loads rows r and r + 32,
+  // 4 consecutive floats each
+  const int r = tid / 8, c4 = (tid % 8) * 4;
+  float4 pa[2], pb[2];
+  auto gload = [&](int ch) {
+    const int k0 = ch * kKC + c4;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      pa[h] = *reinterpret_cast<const float4 *>(Xf + (size_t)(bi + r + 32 * h) * ldk + k0);
+      pb[h] = *reinterpret_cast<const float4 *>(Xf + (size_t)(bj + r + 32 * h) * ldk + k0);
+    }
+  };
   floatx4 acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < ldk; k0 += kKC) {
-    // 64 rows x 16 floats per operand: thread tid loads 4 consecutive floats
-    {
-      const int r = tid / 4, c4 = (tid % 4) * 4;
-      const float4 va = *reinterpret_cast<const float4 *>(Xf + (size_t)(bi + r) * ldk + k0 + c4);
-      const float4 vb = *reinterpret_cast<const float4 *>(Xf + (size_t)(bj + r) * ldk + k0 + c4);
-      As[r][c4 + 0] = va.x; As[r][c4 + 1] = va.y; As[r][c4 + 2] = va.z; As[r][c4 + 3] = va.w;
-      Bs[r][c4 + 0] = vb.x; Bs[r][c4 + 1] = vb.y; Bs[r][c4 + 2] = vb.z; Bs[r][c4 + 3] = vb.w;
+  if (c0 < c1) gload(c0);
+  for (int ch = c0; ch < c1; ++ch) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float *ar = &As[r + 32 * h][c4], *br = &Bs[r + 32 * h][c4];
+      ar[0] = pa[h].x; ar[1] = pa[h].y; ar[2] = pa[h].z; ar[3] = pa[h].w;
+      br[0] = pb[h].x; br[1] = pb[h].y; br[2] = pb[h].z; br[3] = pb[h].w;
     }
     __syncthreads();
+    if (ch + 1 < c1) gload(ch + 1);
 #pragma unroll
     for (int kk = 0; kk < kKC; kk += 4) {
       const float a = As[wave * 16 + lane % 16][kk + lane / 16];
@@ -149,12 +169,26 @@ __global__ __launch_bounds__(256) void k_gram_d2(int n, int n_pad, int ldk, cons
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = bi + wave * 16 + 4 * (lane / 16) + r;
+    for (int q = 0; q < 4; ++q) {
+      const int i = bi + wave * 16 + 4 * (lane / 16) + q;
       const int j = bj + c * 16 + lane % 16;
-      if (i < n && j < n) D2[(size_t)i * ldd + j] = nrm[i] + nrm[j] - 2.0f * acc[c][r];
+      if (nsplit > 1)
+        part[((size_t)blockIdx.z * n_pad + i) * n_pad + j] = acc[c][q];
+      else if (i < n && j < n)
+        D2[(size_t)i * ldd + j] = nrm[i] + nrm[j] - 2.0f * acc[c][q];
     }
   }
+}
+
+// d2 from the K-split partial Gram tiles, splits added in order.
+__global__ void k_gram_combine(int n, int n_pad, int nsplit, const float *part, const float *nrm,
+                               float *D2, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+  float g = 0.f;
+  for (int z = 0; z < nsplit; ++z) g += part[((size_t)z * n_pad + i) * n_pad + j];
+  D2[(size_t)i * ldd + j] = nrm[i] + nrm[j] - 2.0f * g;
 }
 
 // Monotone map of a float to an unsigned key (handles negative values).
@@ -475,9 +509,20 @@ static cc_status knn_lists(int64_t n, int64_t p, const TI *X, int64_t ldx, const
                      Xf.as<float>(), Xd.as<double>());
   hipLaunchKernelGGL(k_rownorm, dim3((int)n_pad), dim3(256), 0, st, (int)n_pad, (int)ldk,
                      Xf.as<float>(), nrm.as<float>());
+  // split K until the launch has about 4 blocks per CU (at most 8 splits)
   const int gb = (int)(n_pad / kGT);
-  hipLaunchKernelGGL(k_gram_d2, dim3(gb, gb), dim3(256), 0, st, (int)n, (int)n_pad, (int)ldk,
-                     Xf.as<float>(), nrm.as<float>(), D2.as<float>(), (int64_t)n);
+  const int nch = (int)(ldk / kKC);
+  int nsplit = (int)std::min<int64_t>(std::min<int64_t>(cdiv64(1024, (int64_t)gb * gb), 8), nch);
+  if (nsplit < 1) nsplit = 1;
+  DevBuf part;
+  if (nsplit > 1) KN_TRY(part.alloc((size_t)nsplit * n_pad * n_pad * 4));
+  hipLaunchKernelGGL(k_gram_d2, dim3(gb, gb, nsplit), dim3(256), 0, st, (int)n, (int)n_pad, (int)ldk,
+                     nsplit, Xf.as<float>(), nrm.as<float>(), D2.as<float>(), (int64_t)n,
+                     part.as<float>());
+  if (nsplit > 1)
+    hipLaunchKernelGGL(k_gram_combine, dim3((int)cdiv64(n * n, 256)), dim3(256), 0, st, (int)n,
+                       (int)n_pad, nsplit, part.as<float>(), nrm.as<float>(), D2.as<float>(),
+                       (int64_t)n);
   CC_HIP(hipGetLastError());
   const size_t lds = (size_t)npow2 * 8;
   CC_HIP(hipFuncSetAttribute((const void *)k_row_candidates,
