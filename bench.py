@@ -100,15 +100,16 @@ def stored_traffic(workload, precision):
     none for this workload or the kernel sources changed since it was taken."""
     if workload != "expression" or precision != "mixed" or not os.path.exists(TRAFFIC_PROFILE):
         return None
-    text = open(TRAFFIC_PROFILE).read()
-    m = re.search(r"```json\n(.*?)\n```", text, re.S)
-    if not m:
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        m = re.search(r"```json\n(.*?)\n```", text, re.S)
+        rec = json.loads(m.group(1)) if m else {}
+        if rec.get("source_sha256") != kernel_source_hash():
+            return None
+        return rec["fetch_kib_per_launch"] * rec["fetch_factor"] * 1024 + \
+            rec["write_kib_per_launch"] * rec["write_factor"] * 1024
+    except (OSError, ValueError, KeyError, TypeError):
         return None
-    rec = json.loads(m.group(1))
-    if rec.get("source_sha256") != kernel_source_hash():
-        return None
-    return rec["fetch_kib_per_launch"] * rec["fetch_factor"] * 1024 + \
-        rec["write_kib_per_launch"] * rec["write_factor"] * 1024
 
 
 def pmc_summary(fetch_csv, write_csv, copy_mib, command):
@@ -202,6 +203,19 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q))
 
 
+def _accuracy(infos):
+    """Share of solves whose stopping test passed, and the stopping rule's
+    quantity at the last test (windowed change of U and A over max(1, ||U||),
+    compared against tol * eta): how far capped solves are from stopping."""
+    import numpy as np
+    rc = np.array([i["rel_change"] for i in infos], dtype=np.float64)
+    conv = np.array([i["converged"] for i in infos], dtype=np.float64)
+    return {"converged_frac": float(conv.mean()) if conv.size else 0.0,
+            "rel_change_median": float(np.median(rc)) if rc.size else 0.0,
+            "rel_change_max": float(rc.max()) if rc.size else 0.0,
+            "stop_threshold": 1e-6 * 1e-2}
+
+
 def bench_batched(args):
     """Batched instances in shared launches against the plain per-solve path."""
     import numpy as np
@@ -253,6 +267,7 @@ def bench_batched(args):
         "solves_per_s": solves / wall, "wall_s": wall,
         "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99), "max": float(np.max(lat))},
         "mm_iterations": int(sum(i["iters"] for inf in infos for i in inf)),
+        "accuracy": _accuracy([i for inf in infos for i in inf]),
         "plain": {"sample": len(times), "solves_per_s": psolves / sum(times), "mean_path_s": mean_path,
                   "fifo_latency_ms_estimated": {"p50": 1e3 * _pct(fifo, 50), "p99": 1e3 * _pct(fifo, 99)}},
     }
@@ -288,10 +303,11 @@ def bench_served(args):
             time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
     wall = time.perf_counter() - t0
     lat = [srv.status(tickets[r])["t_done"] - srv.status(tickets[r])["t_submit"] for r in range(N)]
+    sinfos = [i for r in range(N) for i in srv.result(tickets[r])[1]]
     srv.close()
     print(f"[bench] served: {N} requests in {wall:.2f}s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    lat2 = []
+    lat2, pinfos = [], []
     for r, w in enumerate(reqs):
         now = time.perf_counter() - t0
         if now < arr[r]:
@@ -300,7 +316,7 @@ def bench_served(args):
         M = torch.tensor(w.mask.astype(np.uint8), device="cuda")
         e, wt, _ = cc.build_knn_weights(X, M, k=w.k, phi=w.phi)
         with cc.Problem(X, M, e, wt, precision="mixed") as pr:
-            pr.solve_path([float(g) for g in w.gammas], labels=True, **opts)
+            pinfos += pr.solve_path([float(g) for g in w.gammas], labels=True, **opts)[0]
         torch.cuda.synchronize()
         lat2.append(time.perf_counter() - t0 - arr[r])
     wall2 = time.perf_counter() - t0
@@ -308,9 +324,9 @@ def bench_served(args):
     return {
         "requests": N, "arrival_rate_per_s": 200.0, "solves": solves, "max_iter_per_gamma": args.serve_max_iter,
         "server": {"solves_per_s": solves / wall, "requests_per_s": N / wall,
-                   "latency_s": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)}},
+                   "latency_s": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)}, "accuracy": _accuracy(sinfos)},
         "plain_fifo": {"solves_per_s": solves / wall2, "requests_per_s": N / wall2,
-                       "latency_s": {"p50": _pct(lat2, 50), "p99": _pct(lat2, 99)}},
+                       "latency_s": {"p50": _pct(lat2, 50), "p99": _pct(lat2, 99)}, "accuracy": _accuracy(pinfos)},
     }
 
 

@@ -54,3 +54,12 @@ def test_counter_summary_scales_by_the_copy_and_checks_the_source_hash(tmp_path,
     assert bench.stored_traffic("genotype", "mixed") is None
     prof.write_text(text.replace(bench.kernel_source_hash(), "0" * 64))
     assert bench.stored_traffic("expression", "mixed") is None
+
+
+def test_malformed_counter_summary_gives_no_traffic(tmp_path, monkeypatch):
+    prof = tmp_path / "traffic.md"
+    prof.write_text("```json\n{not json\n```\n")
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    assert bench.stored_traffic("expression", "mixed") is None
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
+    assert bench.stored_traffic("expression", "mixed") is None
