@@ -2473,10 +2473,11 @@ static cc_status build_launch_set(LaunchSet &L, const std::vector<Problem *> &pr
 }
 
 // Launch tables and the graph of graph_iters iterations for (vec, ipw).
-static cc_status batch_configure(Batch *B, int vec, int ipw) {
+static cc_status batch_configure(Batch *B, int vec, int ipw, const std::vector<int> *order = nullptr) {
   std::vector<const BatchInst *> bis;
   for (size_t b = 0; b < B->probs.size(); ++b) bis.push_back(B->bi + b);
-  CC_TRY(build_launch_set(B->ls, B->probs, bis, B->order, vec, ipw, B->opts.test_every, B->stream));
+  CC_TRY(build_launch_set(B->ls, B->probs, bis, order ? *order : B->order, vec, ipw, B->opts.test_every,
+                          B->stream));
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   B->gexec = nullptr;
@@ -2664,6 +2665,12 @@ cc_status batch_create(int32_t n_inst, Problem *const *probs, const int32_t *n_g
   return CC_OK;
 }
 
+// Path-finished flag of each instance, read from its scalar slot 0.
+__global__ void k_gather_finished(int n, DevScalars *const *sc0, int *out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = sc0[k]->finished;
+}
+
 cc_status batch_run(Batch *B, int32_t *labels, cc_solve_info *infos, double *latency_ms) {
   const int n_inst = (int)B->probs.size();
   CC_TRY(batch_start(B));
@@ -2672,13 +2679,49 @@ cc_status batch_run(Batch *B, int32_t *labels, cc_solve_info *infos, double *lat
   for (int b = 0; b < n_inst; ++b)
     budget = std::max<int64_t>(budget, (int64_t)B->n_gamma[b] * ((int64_t)B->opts.max_iter + 2));
   const int64_t max_replays = cdiv(budget, B->graph_iters) + 2;
-  bool finished = false;
+  // Compaction: once half of the instances in the current launch tables have
+  // finished their paths, the tables and the graph are rebuilt over the
+  // active ones (after a replay every instance is back on scalar slot 0), so
+  // finished instances stop taking blocks.  Each instance's blocks do the
+  // same work either way.
+  struct Bufs {
+    void *a = nullptr, *b = nullptr;
+    ~Bufs() { if (a) (void)hipFree(a); if (b) (void)hipFree(b); }
+  } tmp;
+  CC_TRY(dmalloc(&tmp.a, (size_t)n_inst * 4));
+  CC_TRY(dmalloc(&tmp.b, (size_t)n_inst * sizeof(DevScalars *)));
+  int32_t *d_fin = (int32_t *)tmp.a;
+  DevScalars **d_sc0 = (DevScalars **)tmp.b;
+  std::vector<DevScalars *> hsc(n_inst);
+  for (int b = 0; b < n_inst; ++b) hsc[b] = B->probs[b]->sc;
+  CC_HIP(hipMemcpyAsync(d_sc0, hsc.data(), hsc.size() * sizeof(DevScalars *), hipMemcpyHostToDevice, B->stream));
+  std::vector<int32_t> hfin(n_inst);
+  int in_set = n_inst;
+  bool finished = false, compacted = false;
   for (int64_t r = 0; r < max_replays; ++r) {
     CC_HIP(hipGraphLaunch(B->gexec, B->stream));
     CC_HIP(hipMemcpyAsync(B->fin_host, B->n_finished, 4, hipMemcpyDeviceToHost, B->stream));
     CC_HIP(hipStreamSynchronize(B->stream));
-    if (B->fin_host[0] >= n_inst) { finished = true; break; }
+    const int done = B->fin_host[0];
+    if (done >= n_inst) { finished = true; break; }
+    if (n_inst - done <= in_set / 2) {
+      hipLaunchKernelGGL(k_gather_finished, dim3((int)cdiv(n_inst, 256)), dim3(256), 0, B->stream, n_inst,
+                         (DevScalars *const *)d_sc0, d_fin);
+      CC_HIP(hipGetLastError());
+      CC_HIP(hipMemcpyAsync(hfin.data(), d_fin, (size_t)n_inst * 4, hipMemcpyDeviceToHost, B->stream));
+      CC_HIP(hipStreamSynchronize(B->stream));
+      std::vector<int> active;
+      for (int b : B->order)
+        if (!hfin[b]) active.push_back(b);
+      if (!active.empty()) {
+        CC_TRY(batch_configure(B, B->ls.vec, B->ls.ipw, &active));
+        in_set = (int)active.size();
+        compacted = true;
+      }
+    }
   }
+  // the next run starts from the full tables
+  if (compacted) CC_TRY(batch_configure(B, B->ls.vec, B->ls.ipw));
   if (!finished) { set_error("batch did not finish within its iteration caps"); return CC_ERR_STATE; }
   // graph_iters is even: every instance is back on scalar slot 0
   std::vector<double> hinfo(B->total_gamma * kInfoVals);
@@ -2751,11 +2794,6 @@ __global__ void k_inst_init(const BatchInst *bi, int max_iter, int K) {
   sc->d_prev = 0.0; sc->dA_prev = 0.0; sc->F_cur = 0.0;
   sc->F_last = 0.0; sc->d_last = 0.0; sc->rel_last = 0.0;
   sc->pending = 0; sc->path_k = 0; sc->finished = 0;
-}
-
-__global__ void k_gather_finished(int n, DevScalars *const *sc0, int *out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) out[k] = sc0[k]->finished;
 }
 
 static double host_seconds() {
