@@ -163,6 +163,8 @@ struct Batch {
   int graph_iters = 32;           // MM iterations per graph replay (even)
   cc_solve_opts opts{};
   hipStream_t stream = nullptr;   // private: graphs are captured on it
+  std::vector<hipStream_t> side;  // edge classes beyond the first, as graph branches
+  std::vector<hipEvent_t> ev;      // fork and join events of those branches
   std::vector<int> order;         // instances by decreasing work
   BatchInst *bi = nullptr;
   std::vector<int> n_gamma;

@@ -2365,29 +2365,46 @@ static void launch_set_point_pf(const LaunchSet &L, int par, hipStream_t st) {
   }
 }
 
+// One iteration of a launch set.  With side streams and events (graph
+// capture), edge classes after the first run on their own streams as
+// parallel branches between the point sweep and the next iteration: the
+// classes cover disjoint instances.
 template <int PREC>
-static void launch_set_p(const LaunchSet &L, int par, hipStream_t st) {
+static void launch_set_p(const LaunchSet &L, int par, hipStream_t st, const hipStream_t *side,
+                         const hipEvent_t *ev) {
   if (L.nblk_point > 0) {
     if (L.ipw > 1) launch_set_point_pf<PREC, true>(L, par, st);
     else launch_set_point_pf<PREC, false>(L, par, st);
   }
-  for (const EdgeClass &c : L.ecls) {
+  const int nc = (int)L.ecls.size();
+  if (side && nc > 1) (void)hipEventRecord(ev[0], st);
+  for (int k = 0; k < nc; ++k) {
+    const EdgeClass &c = L.ecls[k];
+    hipStream_t s = st;
+    if (side && k > 0) {
+      s = side[k - 1];
+      (void)hipStreamWaitEvent(s, ev[0], 0);
+    }
     const dim3 g(c.nblk), t(kEdgeBlock);
     switch (c.nv) {
-      case 1: hipLaunchKernelGGL((k_edge_items_batch<PREC, 1>), g, t, 0, st, c.eargs[par], c.etab); break;
-      case 2: hipLaunchKernelGGL((k_edge_items_batch<PREC, 2>), g, t, 0, st, c.eargs[par], c.etab); break;
-      case 4: hipLaunchKernelGGL((k_edge_items_batch<PREC, 4>), g, t, 0, st, c.eargs[par], c.etab); break;
-      case 8: hipLaunchKernelGGL((k_edge_items_batch<PREC, 8>), g, t, 0, st, c.eargs[par], c.etab); break;
-      default: hipLaunchKernelGGL((k_edge_items_batch<PREC, 16>), g, t, 0, st, c.eargs[par], c.etab); break;
+      case 1: hipLaunchKernelGGL((k_edge_items_batch<PREC, 1>), g, t, 0, s, c.eargs[par], c.etab); break;
+      case 2: hipLaunchKernelGGL((k_edge_items_batch<PREC, 2>), g, t, 0, s, c.eargs[par], c.etab); break;
+      case 4: hipLaunchKernelGGL((k_edge_items_batch<PREC, 4>), g, t, 0, s, c.eargs[par], c.etab); break;
+      case 8: hipLaunchKernelGGL((k_edge_items_batch<PREC, 8>), g, t, 0, s, c.eargs[par], c.etab); break;
+      default: hipLaunchKernelGGL((k_edge_items_batch<PREC, 16>), g, t, 0, s, c.eargs[par], c.etab); break;
     }
+    if (side && k > 0) (void)hipEventRecord(ev[k], s);
   }
+  if (side)
+    for (int k = 1; k < nc; ++k) (void)hipStreamWaitEvent(st, ev[k], 0);
 }
 
 // One MM iteration of every problem of the set (scalar-slot parity par).
-static void launch_set_iteration(const LaunchSet &L, int prec, int par, hipStream_t st) {
-  if (prec == kF32) launch_set_p<kF32>(L, par, st);
-  else if (prec == kF64) launch_set_p<kF64>(L, par, st);
-  else launch_set_p<kMixed>(L, par, st);
+static void launch_set_iteration(const LaunchSet &L, int prec, int par, hipStream_t st,
+                                 const hipStream_t *side = nullptr, const hipEvent_t *ev = nullptr) {
+  if (prec == kF32) launch_set_p<kF32>(L, par, st, side, ev);
+  else if (prec == kF64) launch_set_p<kF64>(L, par, st, side, ev);
+  else launch_set_p<kMixed>(L, par, st, side, ev);
 }
 
 template <typename T>
@@ -2482,8 +2499,20 @@ static cc_status batch_configure(Batch *B, int vec, int ipw, const std::vector<i
   if (B->graph) (void)hipGraphDestroy(B->graph);
   B->gexec = nullptr;
   B->graph = nullptr;
+  const size_t nc = B->ls.ecls.size();
+  while (B->side.size() + 1 < nc) {
+    hipStream_t s;
+    CC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    B->side.push_back(s);
+  }
+  while (B->ev.size() < std::max<size_t>(nc, 1)) {
+    hipEvent_t e;
+    CC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    B->ev.push_back(e);
+  }
   CC_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-  for (int it = 0; it < B->graph_iters; ++it) launch_set_iteration(B->ls, B->precision, it & 1, B->stream);
+  for (int it = 0; it < B->graph_iters; ++it)
+    launch_set_iteration(B->ls, B->precision, it & 1, B->stream, B->side.data(), B->ev.data());
   CC_HIP(hipStreamEndCapture(B->stream, &B->graph));
   CC_HIP(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
   return CC_OK;
@@ -2529,6 +2558,8 @@ void batch_free(Batch *B) {
     if (b) (void)hipFree(b);
   if (B->fin_host) (void)hipHostFree(B->fin_host);
   if (B->stream) (void)hipStreamDestroy(B->stream);
+  for (hipStream_t s : B->side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : B->ev) (void)hipEventDestroy(e);
   delete B;
 }
 
