@@ -32,20 +32,27 @@ def sq_distances_row(Xt: np.ndarray, i: int) -> np.ndarray:
     return (diff * diff).sum(axis=1)
 
 
-def knn_lists(Xt: np.ndarray, k: int) -> np.ndarray:
-    """(n, k) neighbour indices of each point, nearest first, ties to the
-    lower index, self excluded."""
+def knn_rows(Xt: np.ndarray, k: int, rows) -> np.ndarray:
+    """(len(rows), k) neighbour indices of the given points, nearest first,
+    ties to the lower index, self excluded."""
     n = Xt.shape[0]
     if not (1 <= k < n):
         raise ValueError("need 1 <= k < n")
-    out = np.empty((n, k), dtype=np.int64)
+    rows = np.asarray(rows, dtype=np.int64).reshape(-1)
+    out = np.empty((rows.size, k), dtype=np.int64)
     idx = np.arange(n)
-    for i in range(n):
+    for r, i in enumerate(rows.tolist()):
         d2 = sq_distances_row(Xt, i)
         d2[i] = np.inf
         order = np.lexsort((idx, d2))  # primary d2, secondary index
-        out[i] = order[:k]
+        out[r] = order[:k]
     return out
+
+
+def knn_lists(Xt: np.ndarray, k: int) -> np.ndarray:
+    """(n, k) neighbour indices of each point, nearest first, ties to the
+    lower index, self excluded."""
+    return knn_rows(Xt, k, np.arange(Xt.shape[0]))
 
 
 def knn_edges(Xt: np.ndarray, k: int):

@@ -145,3 +145,35 @@ def test_batched_full_size_sampled_instances_equal_alone(cc, monkeypatch):
             for k in range(len(g)):
                 if rinf[k]["converged"]:
                     assert np.array_equal(labs[b][k].cpu().numpy(), rlab[k].cpu().numpy()), (b, k)
+
+
+def test_knn_at_the_largest_supported_n(cc):
+    """n = 16384 (the kNN builder's limit; a 1 GB FP32 distance matrix), p = 16,
+    k = 10, literal phi: the edge list is sorted with i < j, and for sampled
+    points the edges are exactly the union relation of the oracle's nearest
+    neighbours, with the oracle's weights."""
+    wl = gen.plain(n=16384, p=16)
+    X = as_f32_values(wl.X)
+    n, k = X.shape[0], 10
+    e, w, phi_used = cc.build_knn_weights(torch.tensor(X, dtype=torch.float32, device="cuda"), None, k=k, phi=0.5)
+    E = e.cpu().numpy().astype(np.int64)
+    W = w.cpu().numpy()
+    assert phi_used == 0.5
+    assert np.all(E[:, 0] < E[:, 1])
+    key = E[:, 0] * n + E[:, 1]
+    assert np.all(np.diff(key) > 0)
+    rng = np.random.default_rng(16384)
+    sample = rng.choice(n, 12, replace=False)
+    own = weights.knn_rows(X, k, sample)
+    for r, i in enumerate(sample.tolist()):
+        sel = (E[:, 0] == i) | (E[:, 1] == i)
+        adj = set(np.where(E[sel, 0] == i, E[sel, 1], E[sel, 0]).tolist())
+        assert set(own[r].tolist()) <= adj, i
+        extra = sorted(adj - set(own[r].tolist()))
+        if extra:
+            back = weights.knn_rows(X, k, extra)
+            for q, j in enumerate(extra):
+                assert i in set(back[q].tolist()), (i, j)
+        for ee in np.where(sel)[0].tolist():
+            d = X[E[ee, 1]] - X[E[ee, 0]]
+            assert W[ee] == pytest.approx(np.exp(-0.5 * float((d * d).sum())), rel=1e-12)

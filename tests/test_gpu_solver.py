@@ -79,7 +79,8 @@ def test_plain_config_f64_gamma_1(cc):
     assert ncl == info.n_clusters == gi["n_clusters"]
 
 
-@pytest.mark.parametrize("gamma", [1.0, 10.0, 100.0])
+# gamma = 1000 fuses every edge of each kNN component (full coalescence)
+@pytest.mark.parametrize("gamma", [1.0, 10.0, 100.0, 1000.0])
 def test_plain_config_mixed_converged(cc, gamma):
     X, M, E, w = plain_problem()
     X = as_f32_values(X)
