@@ -655,14 +655,26 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     };
     // the first chunk is straight-line code after the loads above, so its
     // gathers wait only on the slot loads
+    // a point with more than 64 neighbours (waves with one item): the next
+    // 64 slots load now, while the first 64 gather, not after them
+    int jn = -1;
+    double qn = 0.0;
+    if (!PF && __popcll(__ballot(jl >= 0)) == kWave && lane < a.ell_s - kWave) {
+      jn = a.colE[rs + kWave + lane];
+      if (m > 0) qn = a.qE[rs + kWave + lane];
+    }
     int deg = chunk(rs, jl, ql);
     if (deg == kWave) {
       for (int k64 = kWave; k64 < a.ell_s; k64 += kWave) {
-        int jk = -1;
-        double qk = 0.0;
-        if (lane < a.ell_s - k64) {
-          jk = a.colE[rs + k64 + lane];
-          if (m > 0) qk = a.qE[rs + k64 + lane];
+        int jk = jn;
+        double qk = qn;
+        if (PF || k64 > kWave) {
+          jk = -1;
+          qk = 0.0;
+          if (lane < a.ell_s - k64) {
+            jk = a.colE[rs + k64 + lane];
+            if (m > 0) qk = a.qE[rs + k64 + lane];
+          }
         }
         const int cnt = chunk(rs + k64, jk, qk);
         deg += cnt;
