@@ -358,12 +358,8 @@ def bench_extras(X, M, edges, w, gammas, args):
     rng = np.random.default_rng(7)
     n = X.shape[0]
     Y = torch.tensor(np.stack([rng.uniform(-60, 60, n), rng.uniform(-180, 180, n)], axis=1), device="cuda")
-    Xc = X if M is None else X.clone()
-    if M is not None:  # the composite distance takes complete data: mean-impute
-        mf = M.to(torch.float32)
-        mean = (Xc * mf).sum(0) / mf.sum(0).clamp(min=1)
-        Xc = torch.where(M.bool(), Xc, mean.expand_as(Xc)).contiguous()
-    _, comp_ms = timed(lambda: cc.composite_weights(edges, Xc, Y, 0.5, -0.5, geodesic=True, radius=6371.0))
+    _, comp_ms = timed(lambda: cc.composite_weights(edges, X, Y, 0.5, -0.5, geodesic=True, radius=6371.0,
+                                                    mask=M))
     opts = dict(max_iter=args.extras_max_iter, labels=True)
     with cc.Problem(X, M, edges, w, precision="mixed") as g:
         (_, _, Up), _ = timed(lambda: g.solve_path(gammas, U_path=True, **opts))

@@ -415,8 +415,9 @@ cc_status cc_server_destroy(cc_server_t server);
  * cc_composite_weights: weights w_e = exp(-phi d_e^2) over given edges
  * (device ei, ej, n_edges) from the composite distance of eq
  * composite_distance, d_ij = alpha ||x_i - x_j|| + (1 - alpha) dist(y_i, y_j)
- * with X (device, x_dtype, n rows of ldx, p columns, no missing entries:
- * impute first; p may be 0) and coordinates Y (device FP64, n rows of ldy,
+ * with X (device, x_dtype, n rows of ldx, p columns; p may be 0) and mask
+ * (device, may be NULL: missing entries take their observed column mean, as
+ * for cc_build_knn_weights) and coordinates Y (device FP64, n rows of ldy,
  * q <= 8 columns).  dist is Euclidean over the coordinates, a coordinate
  * with period[t] > 0 (host, q entries, may be NULL) taken modulo that period
  * (the shorter way round); geodesic != 0 needs q = 2 and takes (latitude,
@@ -437,7 +438,8 @@ cc_status cc_min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *
                              void *stream);
 cc_status cc_composite_weights(int64_t n, int64_t n_edges, const int32_t *ei,
                                const int32_t *ej, int64_t p, int32_t x_dtype,
-                               const void *X, int64_t ldx, int32_t q,
+                               const void *X, int64_t ldx, const uint8_t *mask,
+                               int64_t ldm, int32_t q,
                                const double *Y, int64_t ldy, const double *period,
                                int32_t geodesic, double radius, double alpha,
                                double phi, int32_t normalize, double *w,

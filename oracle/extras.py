@@ -102,9 +102,12 @@ def coord_distance(yi, yj, period=None, geodesic=False, radius=1.0) -> float:
 
 
 def composite_weights(X: np.ndarray, Y: np.ndarray, edges: np.ndarray, alpha: float, phi: float,
-                      period=None, geodesic=False, radius=1.0, normalize=False):
-    """(w (E,), phi_used) over the given edges."""
+                      period=None, geodesic=False, radius=1.0, normalize=False, mask=None):
+    """(w (E,), phi_used) over the given edges; with a mask, distances of X
+    on its mean-imputed copy (as the kNN weights)."""
     X = np.asarray(X, dtype=np.float64)
+    if mask is not None:
+        X = impute_column_means(X, mask)
     Y = np.asarray(Y, dtype=np.float64).reshape(X.shape[0], -1)
     E = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
     d2 = np.empty(E.shape[0])

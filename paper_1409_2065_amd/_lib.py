@@ -84,7 +84,7 @@ SIGNATURES = {
     "cc_solve_path_pc": (i32, [vp, i32, P_f64, C.POINTER(SolveOpts), vp, i32, vp, vp, vp,
                                C.POINTER(SolveInfo)]),
     "cc_min_connected_k": (i32, [i64, i64, i32, vp, i64, vp, i64, i32, P_i32, P_i32, vp]),
-    "cc_composite_weights": (i32, [i64, i64, vp, vp, i64, i32, vp, i64, i32, vp, i64, P_f64, i32,
+    "cc_composite_weights": (i32, [i64, i64, vp, vp, i64, i32, vp, i64, vp, i64, i32, vp, i64, P_f64, i32,
                                    f64, f64, f64, i32, vp, P_f64, vp]),
     "cc_batch_create": (i32, [i32, C.POINTER(vp), P_i32, P_f64, C.POINTER(SolveOpts), i32, C.POINTER(vp)]),
     "cc_batch_run": (i32, [vp, vp, C.POINTER(SolveInfo), P_f64]),

@@ -262,9 +262,10 @@ def min_connected_k(X, mask=None, k_max: int = 32):
 
 
 def composite_weights(edges, X, Y, alpha: float, phi: float = -0.5, period=None,
-                      geodesic: bool = False, radius: float = 1.0, normalize: bool = False):
+                      geodesic: bool = False, radius: float = 1.0, normalize: bool = False, mask=None):
     """cc_composite_weights: (w (E,) float64 on the device, phi_used) from
-    d = alpha ||x_i - x_j|| + (1 - alpha) dist(y_i, y_j) over the edges."""
+    d = alpha ||x_i - x_j|| + (1 - alpha) dist(y_i, y_j) over the edges
+    (missing entries of X, per mask, take their observed column means)."""
     e = _dev(edges, torch.int32).reshape(-1, 2)
     ei = e[:, 0].contiguous()
     ej = e[:, 1].contiguous()
@@ -273,6 +274,7 @@ def composite_weights(edges, X, Y, alpha: float, phi: float = -0.5, period=None,
     if Y.dim() == 1:
         Y = Y.reshape(-1, 1)
     n, p = X.shape
+    m = _mask(mask, X.shape)
     q = Y.shape[1]
     if Y.shape[0] != n:
         raise ValueError("X and Y need the same number of rows")
@@ -282,7 +284,7 @@ def composite_weights(edges, X, Y, alpha: float, phi: float = -0.5, period=None,
     w = torch.empty(e.shape[0], dtype=torch.float64, device="cuda")
     phi_used = C.c_double()
     check(_lib.load().cc_composite_weights(
-        n, e.shape[0], _ptr(ei), _ptr(ej), p, _xdtype(X), _ptr(X), p, q, _ptr(Y), q,
+        n, e.shape[0], _ptr(ei), _ptr(ej), p, _xdtype(X), _ptr(X), p, _ptr(m), p, q, _ptr(Y), q,
         None if per is None else per.ctypes.data_as(_lib.P_f64), 1 if geodesic else 0, float(radius),
         float(alpha), float(phi), 1 if normalize else 0, _ptr(w), C.byref(phi_used),
         C.c_void_p(_stream())))

@@ -527,12 +527,13 @@ cc_status cc_min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *
 }
 
 cc_status cc_composite_weights(int64_t n, int64_t n_edges, const int32_t *ei, const int32_t *ej,
-                               int64_t p, int32_t x_dtype, const void *X, int64_t ldx, int32_t q,
+                               int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
+                               const uint8_t *mask, int64_t ldm, int32_t q,
                                const double *Y, int64_t ldy, const double *period,
                                int32_t geodesic, double radius, double alpha, double phi,
                                int32_t normalize, double *w, double *phi_used, void *stream) {
   CC_GUARD_BEGIN
-  return composite_weights(n, n_edges, ei, ej, p, x_dtype, X, ldx, q, Y, ldy, period, geodesic,
+  return composite_weights(n, n_edges, ei, ej, p, x_dtype, X, ldx, mask, ldm, q, Y, ldy, period, geodesic,
                            radius, alpha, phi, normalize, w, phi_used, (hipStream_t)stream);
   CC_GUARD_END
 }

@@ -292,7 +292,8 @@ cc_status min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *X,
                           hipStream_t stream);
 cc_status composite_weights(int64_t n, int64_t n_edges, const int32_t *ei,
                             const int32_t *ej, int64_t p, int32_t x_dtype,
-                            const void *X, int64_t ldx, int32_t q,
+                            const void *X, int64_t ldx, const uint8_t *mask,
+                            int64_t ldm, int32_t q,
                             const double *Y, int64_t ldy, const double *period,
                             int32_t geodesic, double radius, double alpha,
                             double phi, int32_t normalize, double *w,

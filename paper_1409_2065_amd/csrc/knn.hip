@@ -403,6 +403,17 @@ __global__ void k_keep_prefix(int64_t m, int kmax, int k, uint8_t *keep) {
 }
 
 // ------------------------------------------------ composite distance
+// Mean-imputed X in FP64 (n x p dense): missing entries take their
+// observed column mean, as the kNN weights do.
+template <typename TI>
+__global__ void k_impute_d(int n, int p, const TI *X, int64_t ldx, const uint8_t *M, int64_t ldm,
+                           const double *mean, double *Xd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * p) return;
+  const int i = (int)(e / p), f = (int)(e - (int64_t)i * p);
+  Xd[e] = M[(size_t)i * ldm + f] ? (double)X[(size_t)i * ldx + f] : mean[f];
+}
+
 constexpr int kMaxCoords = 8;
 struct CoordSpec {
   int q, geodesic;
@@ -666,7 +677,8 @@ cc_status min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *X, 
 }
 
 cc_status composite_weights(int64_t n, int64_t n_edges, const int32_t *ei, const int32_t *ej,
-                            int64_t p, int32_t x_dtype, const void *X, int64_t ldx, int32_t q,
+                            int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
+                            const uint8_t *mask, int64_t ldm, int32_t q,
                             const double *Y, int64_t ldy, const double *period, int32_t geodesic,
                             double radius, double alpha, double phi, int32_t normalize, double *w,
                             double *phi_used, hipStream_t st) {
@@ -674,6 +686,8 @@ cc_status composite_weights(int64_t n, int64_t n_edges, const int32_t *ei, const
   if (n_edges > ((int64_t)1 << 31) - 1 || n > ((int64_t)1 << 31) - 1) { set_error("n or n_edges too large"); return CC_ERR_INVALID_ARG; }
   if (n_edges > 0 && (!ei || !ej || !w)) { set_error("NULL edge or weight array"); return CC_ERR_INVALID_ARG; }
   if (p > 0 && (!X || ldx < p)) { set_error("X is NULL or ldx < p"); return CC_ERR_INVALID_ARG; }
+  if (mask && p > 0 && ldm < p) { set_error("ldm < p"); return CC_ERR_INVALID_ARG; }
+  if (n * p > ((int64_t)1 << 31) - 1) { set_error("n * p too large"); return CC_ERR_INVALID_ARG; }
   if (x_dtype != CC_DTYPE_F32 && x_dtype != CC_DTYPE_F64) { set_error("bad x_dtype"); return CC_ERR_INVALID_ARG; }
   if (q < 0 || q > kMaxCoords) { set_error("need 0 <= q <= 8 coordinates"); return CC_ERR_INVALID_ARG; }
   if (q > 0 && (!Y || ldy < q)) { set_error("Y is NULL or ldy < q"); return CC_ERR_INVALID_ARG; }
@@ -700,16 +714,47 @@ cc_status composite_weights(int64_t n, int64_t n_edges, const int32_t *ei, const
         return CC_ERR_INVALID_ARG;
       }
   }
+  // with a mask: distances on the mean-imputed matrix (FP64)
+  DevBuf mean, bad, Xd;
+  const void *Xuse = X;
+  int64_t ldu = ldx;
+  int32_t tuse = x_dtype;
+  if (mask && p > 0 && n_edges > 0) {
+    KN_TRY(mean.alloc(p * 8));
+    KN_TRY(bad.alloc(4));
+    KN_TRY(Xd.alloc((size_t)n * p * 8));
+    CC_HIP(hipMemsetAsync(bad.p, 0, 4, st));
+    const int cb = (int)cdiv64(p, 256), eb = (int)cdiv64(n * p, 256);
+    if (x_dtype == CC_DTYPE_F32) {
+      hipLaunchKernelGGL((k_col_moments<float>), dim3(cb), dim3(256), 0, st, (int)n, (int)p, (const float *)X,
+                         ldx, mask, ldm, mean.as<double>(), (double *)nullptr, bad.as<int>());
+      hipLaunchKernelGGL((k_impute_d<float>), dim3(eb), dim3(256), 0, st, (int)n, (int)p, (const float *)X, ldx,
+                         mask, ldm, mean.as<double>(), Xd.as<double>());
+    } else {
+      hipLaunchKernelGGL((k_col_moments<double>), dim3(cb), dim3(256), 0, st, (int)n, (int)p, (const double *)X,
+                         ldx, mask, ldm, mean.as<double>(), (double *)nullptr, bad.as<int>());
+      hipLaunchKernelGGL((k_impute_d<double>), dim3(eb), dim3(256), 0, st, (int)n, (int)p, (const double *)X, ldx,
+                         mask, ldm, mean.as<double>(), Xd.as<double>());
+    }
+    CC_HIP(hipGetLastError());
+    int hbad = 0;
+    CC_HIP(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    if (hbad) { set_error("observed X has non-finite entries"); return CC_ERR_INVALID_ARG; }
+    Xuse = Xd.p;
+    ldu = p;
+    tuse = CC_DTYPE_F64;
+  }
   DevBuf d2;
   KN_TRY(d2.alloc(n_edges * 8));
   if (n_edges > 0) {
     const int blocks = (int)cdiv64(n_edges, 4);
-    if (x_dtype == CC_DTYPE_F32)
+    if (tuse == CC_DTYPE_F32)
       hipLaunchKernelGGL((k_edge_composite<float>), dim3(blocks), dim3(256), 0, st, (int)n_edges,
-                         (int)p, (const float *)X, ldx, Y, ldy, c, ei, ej, d2.as<double>());
+                         (int)p, (const float *)Xuse, ldu, Y, ldy, c, ei, ej, d2.as<double>());
     else
       hipLaunchKernelGGL((k_edge_composite<double>), dim3(blocks), dim3(256), 0, st, (int)n_edges,
-                         (int)p, (const double *)X, ldx, Y, ldy, c, ei, ej, d2.as<double>());
+                         (int)p, (const double *)Xuse, ldu, Y, ldy, c, ei, ej, d2.as<double>());
     CC_HIP(hipGetLastError());
   }
   return finish_weights(n_edges, d2.as<double>(), phi, normalize, w, phi_used, st);

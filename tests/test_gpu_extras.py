@@ -141,6 +141,21 @@ def test_composite_weights_match_oracle(cc, alpha, phi, mode, normalize):
     assert np.allclose(w.cpu().numpy(), w0, rtol=1e-12, atol=0)
 
 
+def test_composite_weights_with_missing_entries_match_oracle(cc):
+    wl = gen.expression(seed=1002, n=150, p=30, n_clusters=6, n_gamma=2)
+    X = as_f32_values(wl.X)
+    M = wl.mask
+    edges, _, _ = weights.knn_weights(X, M, 8, -0.5)
+    rng = np.random.default_rng(5)
+    Y = np.stack([rng.uniform(-60, 60, X.shape[0]), rng.uniform(-180, 180, X.shape[0])], axis=1)
+    w0, phi0 = extras.composite_weights(X, Y, edges, 0.5, -0.5, geodesic=True, radius=6371.0, mask=M)
+    Xt, m = _x_dev(X, M)
+    w, phi_used = cc.composite_weights(torch.tensor(edges, dtype=torch.int32), Xt, torch.tensor(Y), 0.5, -0.5,
+                                       geodesic=True, radius=6371.0, mask=m)
+    assert phi_used == pytest.approx(phi0, rel=1e-12)
+    assert np.allclose(w.cpu().numpy(), w0, rtol=1e-12, atol=0)
+
+
 def test_extras_reject_bad_arguments(cc):
     X = torch.zeros((10, 3), device="cuda")
     with pytest.raises(cc.CCError):

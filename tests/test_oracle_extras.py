@@ -110,3 +110,16 @@ def test_composite_distance_blend_and_alpha_one_reduces_to_knn_weights():
     wc, phic = extras.composite_weights(X, rng.normal(size=(30, 2)), edges, alpha=1.0, phi=-0.5)
     assert phic == pytest.approx(phik, rel=1e-14)
     assert np.allclose(wc, wk, rtol=1e-13)
+
+
+def test_composite_distance_with_missing_entries_uses_the_knn_imputation():
+    # alpha = 1 with a mask gives the kNN weights of the same masked data
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(40, 7))
+    M = rng.random(X.shape) > 0.1
+    Xn = np.where(M, X, np.nan)
+    edges, wk, phik = weights.knn_weights(Xn, M, 5, -0.5)
+    wc, phic = extras.composite_weights(np.where(M, X, 123.0), np.zeros((40, 1)), edges, alpha=1.0, phi=-0.5,
+                                        mask=M)
+    assert phic == pytest.approx(phik, rel=1e-14)
+    assert np.allclose(wc, wk, rtol=1e-13)
