@@ -82,7 +82,10 @@ def point_sweep_bytes(n, p, E, precision, has_mask):
     return n * p * per_pf + 40 * E, per_pf
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_k_point_expression_n2000_p500_mixed.md")
+TRAFFIC_PROFILES = {
+    ("expression", "mixed"): os.path.join(ROOT, "profiles", "traffic_k_point_expression_n2000_p500_mixed.md"),
+    ("genotype", "mixed"): os.path.join(ROOT, "profiles", "traffic_k_point_genotype_n1000_p20000_mixed.md"),
+}
 KERNEL_SOURCES = ("paper_1409_2065_amd/csrc/solver.hip", "paper_1409_2065_amd/csrc/ccmi_internal.h")
 
 
@@ -102,10 +105,11 @@ def stored_traffic(workload, precision):
     rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, each scaled by what the
     same counter reads for a device copy of known size), or None when there is
     none for this workload or the kernel sources changed since it was taken."""
-    if workload != "expression" or precision != "mixed" or not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILES.get((workload, precision))
+    if path is None or not os.path.exists(path):
         return None
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
         m = re.search(r"```json\n(.*?)\n```", text, re.S)
         rec = json.loads(m.group(1)) if m else {}
         if rec.get("source_sha256") != kernel_source_hash():

@@ -48,10 +48,11 @@ def test_counter_summary_scales_by_the_copy_and_checks_the_source_hash(tmp_path,
     assert "factors 2.0000 and 1.0000" in text
     prof = tmp_path / "traffic.md"
     prof.write_text(text)
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILES", {("expression", "mixed"): str(prof)})
     got = bench.stored_traffic("expression", "mixed")
     assert got == pytest.approx((1001.0 * 2.0 + 501.0) * 1024)
     assert bench.stored_traffic("genotype", "mixed") is None
+    assert bench.stored_traffic("expression", "f64") is None
     prof.write_text(text.replace(bench.kernel_source_hash(), "0" * 64))
     assert bench.stored_traffic("expression", "mixed") is None
 
@@ -59,7 +60,19 @@ def test_counter_summary_scales_by_the_copy_and_checks_the_source_hash(tmp_path,
 def test_malformed_counter_summary_gives_no_traffic(tmp_path, monkeypatch):
     prof = tmp_path / "traffic.md"
     prof.write_text("```json\n{not json\n```\n")
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILES", {("expression", "mixed"): str(prof)})
     assert bench.stored_traffic("expression", "mixed") is None
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILES", {("expression", "mixed"): str(tmp_path / "missing.md")})
     assert bench.stored_traffic("expression", "mixed") is None
+
+
+def test_committed_counter_summaries_parse():
+    # each committed summary holds a record for the point sweep; whether its
+    # source hash is current decides only whether the bench reports it
+    import json
+    import re
+    for (wl, prec), path in bench.TRAFFIC_PROFILES.items():
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", open(path).read(), re.S).group(1))
+        assert "k_point" in rec["kernel"], path
+        assert rec["fetch_kib_per_launch"] > 0 and rec["write_kib_per_launch"] > 0, path
+        assert 1.5 < rec["fetch_factor"] < 2.5 and 0.5 < rec["write_factor"] < 1.5, path
