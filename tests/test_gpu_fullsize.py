@@ -8,7 +8,12 @@ bench times (mixed precision, default tiles and edge kernels).
   1e-6 with the same fused edges).
 * genotype (n=1000, p=20000, standardised): 3 MM iterations against the
   oracle (its D A products at this size take seconds per iteration), and
-  repeated runs are bitwise equal.  The edges here are a seeded union of
+  repeated runs are bitwise equal.
+* expression, late path: the bench's whole 30-gamma path (warm starts,
+  tol 1e-6, its iteration cap), then 3 more MM iterations at the last gamma
+  from the GPU's final state on both sides (the oracle starting from that
+  same state), within the same 2e-6 bar and with the same fused edges; the
+  path's last labels are the min-index components of the fused edges.  The edges here are a seeded union of
   20 random out-neighbours per point (degrees 27-56; the kNN graph of this
   workload has 20-79), with Gaussian weights from the oracle, so that no
   oracle input comes from the GPU's own kNN.
@@ -18,7 +23,7 @@ import pytest
 import torch
 
 import gen
-from oracle import extras, mm, prep, weights
+from oracle import extras, graph, mm, prep, weights
 from tests._gpu import as_f32_values, oracle_jacobi, rel_max, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -57,6 +62,28 @@ def test_expression_full_trajectory_matches_oracle(cc, expression):
         gi = g.solve(10.0, tol=0.0, max_iter=20)
         U, A, s = (t.cpu().numpy() for t in g.get_state())
     assert gi["iters"] == 20
+    assert rel_max(U, st.U) < 2e-6
+    assert rel_max(A, st.A) < 2e-6
+    assert np.abs(s - st.s).max() < 1e-6
+    assert np.array_equal(s == 0, st.s == 0)
+
+
+def test_expression_late_path_iterations_match_oracle(cc, expression):
+    wl, X, E, w, _ = expression
+    gam = [float(g) for g in wl.gammas]
+    Xt, m, e, wt = to_dev(X, wl.mask, E, w, torch.float32)
+    with cc.Problem(Xt, m, e, wt, precision="mixed") as g:
+        infos, lab, _ = g.solve_path(gam, labels=True, max_iter=20000, warm_start=1)
+        U0, A0, s0 = (t.cpu().numpy() for t in g.get_state())
+        g.set_state(U0, A0, s0)
+        g.solve(gam[-1], tol=0.0, max_iter=3)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    last = lab[-1].cpu().numpy()
+    ref_lab, ncl = graph.components(X.shape[0], E, s0 == 0.0)
+    assert np.array_equal(last, ref_lab)
+    assert infos[-1]["n_clusters"] == ncl and 1 < ncl < X.shape[0]
+    st, _ = oracle_jacobi(X, wl.mask, E, w).solve(
+        gam[-1], mm.Opts(tol=0, max_iter=3, proj="jacobi:1"), mm.State(U0.copy(), s0.copy(), A0.copy()))
     assert rel_max(U, st.U) < 2e-6
     assert rel_max(A, st.A) < 2e-6
     assert np.abs(s - st.s).max() < 1e-6
