@@ -1270,6 +1270,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_tiles(EdgeArgs a) {
 // (a_i - a_j)^2 for up to kEdgesPerThread edges across the group's tiles and
 // writes one partial per (edge, group) for k_edge_reduce.
 constexpr int kEdgesPerThread = 16;
+constexpr int kSlabChunks = 4;  // staged four-feature chunks per thread and tile
 
 template <int PREC, int F>
 __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_group, int ntiles_f) {
@@ -1285,31 +1286,51 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
   const int g = hw_blk().lb;
   const int t0 = g * tiles_per_group, t1 = min(t0 + tiles_per_group, ntiles_f);
   const int E = a.es.E;
-  int ei[kEdgesPerThread], ej[kEdgesPerThread];
+  // both ends of an edge in one word (the slab holds n < 2^16 rows)
+  uint32_t eij[kEdgesPerThread];
   double acc[kEdgesPerThread];
 #pragma unroll
   for (int u = 0; u < kEdgesPerThread; ++u) {
     const int e = threadIdx.x + u * blockDim.x;
-    ei[u] = 0; ej[u] = 0; acc[u] = 0.0;
-    if (e < E) { ei[u] = a.ei[e]; ej[u] = a.ej[e]; }
+    eij[u] = 0u; acc[u] = 0.0;
+    if (e < E) eij[u] = ((uint32_t)a.ei[e] << 16) | (uint32_t)a.ej[e];
   }
-  for (int t = t0; t < t1; ++t) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < a.n * C4; idx += blockDim.x) {
+  // A tile holds n * F / 4 four-feature chunks, at most kSlabChunks per
+  // thread (the host sizes F so that the tile takes at most half the LDS
+  // budget).  A thread issues all its chunk loads before it stores any, so
+  // the staging waits on one HBM latency per tile.  (Carrying the next
+  // tile's chunks through the summation instead spills registers.)
+  const int nch = a.n * C4;
+  TG nv[kSlabChunks][4];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int q = 0; q < kSlabChunks; ++q) {
+      const int idx = threadIdx.x + q * 1024;
       const int row = idx / C4, c = idx - row * C4;
       const int f = t * F + 4 * c;
-      TG v[4] = {(TG)0, (TG)0, (TG)0, (TG)0};
-      if (f < a.ld) RawIO<TG, 4>::load(Gc + (size_t)row * a.ld + f, v);
-      TG *dst = slab + (size_t)row * F + 4 * c;
-      dst[0] = v[0]; dst[1] = v[1]; dst[2] = v[2]; dst[3] = v[3];
+      nv[q][0] = nv[q][1] = nv[q][2] = nv[q][3] = (TG)0;
+      if (idx < nch && f < a.ld) RawIO<TG, 4>::load(Gc + (size_t)row * a.ld + f, nv[q]);
+    }
+  };
+  for (int t = t0; t < t1; ++t) {
+    fetch(t);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSlabChunks; ++q) {
+      const int idx = threadIdx.x + q * 1024;
+      if (idx < nch) {
+        const int row = idx / C4, c = idx - row * C4;
+        TG *dst = slab + (size_t)row * F + 4 * c;
+        dst[0] = nv[q][0]; dst[1] = nv[q][1]; dst[2] = nv[q][2]; dst[3] = nv[q][3];
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kEdgesPerThread; ++u) {
       const int e = threadIdx.x + u * blockDim.x;
       if (e < E) {
-        const TG *ri = slab + (size_t)ei[u] * F;
-        const TG *rj = slab + (size_t)ej[u] * F;
+        const TG *ri = slab + (size_t)(eij[u] >> 16) * F;
+        const TG *rj = slab + (size_t)(eij[u] & 0xffffu) * F;
 #pragma unroll
         for (int f = 0; f < F; ++f) {
           const double d = (double)ri[f] - (double)rj[f];
@@ -1870,7 +1891,7 @@ static void choose_tiles(Problem *P) {
     // small n: stage tiles in LDS and keep per-edge accumulators in registers
     const char *ee = getenv("CCMI_EDGE_SLAB");
     const bool allow = !ee || atoi(ee) != 0;
-    if (allow && P->edge_f > 0 && P->E <= 1024 * 16) {
+    if (allow && P->edge_f > 0 && P->E <= 1024 * 16 && P->n * (P->edge_f / 4) <= kSlabChunks * 1024 && P->n < 65536) {
       P->eslab = true;
       P->eslab_ntf = (int)cdiv(P->ld, P->edge_f);
       P->eslab_tpg = (int)cdiv(P->eslab_ntf, 256);
