@@ -1369,6 +1369,9 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edge_reduce(ReduceArgs a) {
     if (!a.init && lane == 0) in = edge_prefetch(a.es, e);
     const double *pe = a.part + (size_t)e * a.ntile;
     double nb2 = 0.0;
+    // unrolled so that a lane's loads are in flight together; the sum keeps
+    // its order
+#pragma unroll 4
     for (int t = lane; t < a.ntile; t += kWave) nb2 += pe[t];
     nb2 = wave_sum(nb2);
     if (lane == 0) edge_update(a.es, e, nb2, in, a.init, pa, sc, t3);
