@@ -66,6 +66,42 @@ template <> struct Traits<kF64> {
 };
 
 // ------------------------------------------------------ vector load/store
+// Streaming rows of the point sweep (read or written once per iteration):
+// non-temporal accesses, so that they do not push the gathered neighbour
+// rows out of L2.  Used by the sweep with several items per wave (wide
+// rows, whose data do not stay cached); where the whole working set stays
+// in the caches (narrow rows, one item per wave) they measured slower.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+template <typename T, int VEC> struct NtIO {
+  __device__ static void store(T *p, const double (&v)[VEC]) {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) __builtin_nontemporal_store((T)v[k], p + k);
+  }
+};
+template <> struct NtIO<double, 4> {
+  __device__ static void store(double *p, const double (&v)[4]) {
+    nt_d2 a = {v[0], v[1]}, b = {v[2], v[3]};
+    __builtin_nontemporal_store(a, reinterpret_cast<nt_d2 *>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<nt_d2 *>(p + 2));
+  }
+  __device__ static void load(const double *p, double (&o)[4]) {
+    const nt_d2 a = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p));
+    const nt_d2 b = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p + 2));
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+  }
+};
+template <> struct NtIO<float, 4> {
+  __device__ static void store(float *p, const double (&v)[4]) {
+    nt_f4 a = {(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    __builtin_nontemporal_store(a, reinterpret_cast<nt_f4 *>(p));
+  }
+  __device__ static void load(const float *p, float (&o)[4]) {
+    const nt_f4 a = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+  }
+};
+
 template <int VEC> struct VecIO;
 template <> struct VecIO<4> {
   __device__ static void load(const float *p, double (&o)[4]) {
@@ -532,7 +568,8 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
 #pragma unroll
       for (int v = 0; v < VEC; ++v) up0[v] = (TS)0;
     }
-    RawIO<TX, VEC>::load(X + rowc, x0);
+    if constexpr (PF && VEC == 4) NtIO<TX, 4>::load(X + rowc, x0);
+    else RawIO<TX, VEC>::load(X + rowc, x0);
   };
   if (first < it1) preload(first, a.M != nullptr);
 
@@ -590,7 +627,8 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     TG gr[VEC];
     TS apr[VEC];
     RawIO<TG, VEC>::load(Gp + rowc, gr);
-    RawIO<TS, VEC>::load(Ap + rowc, apr);
+    if constexpr (PF && VEC == 4) NtIO<TS, 4>::load(Ap + rowc, apr);
+    else RawIO<TS, VEC>::load(Ap + rowc, apr);
     if (PF && item + kPointWaves < it1) preload(item + kPointWaves, needU);
     double sumg[VEC], sumcg[VEC];
 #pragma unroll
@@ -714,8 +752,13 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
         ps[4] = fma(uu, uu, ps[4]);
         ps[5] = fma(h, g, ps[5]);
       }
-      VecIO<VEC>::store(U + row, u);
-      VecIO<VEC>::store(An + row, an);
+      if constexpr (PF && VEC == 4) {
+        NtIO<TS, 4>::store(U + row, u);
+        NtIO<TS, 4>::store(An + row, an);
+      } else {
+        VecIO<VEC>::store(U + row, u);
+        VecIO<VEC>::store(An + row, an);
+      }
       if (Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, gn);
       if (winU) {
         double us[VEC];
