@@ -186,6 +186,52 @@ def test_objective_descends(missing):
     assert F[-1] < F[0]
 
 
+# ------------------------------------------------------- objective values
+def test_objective_value_at_initial_state():
+    """The initial state (U_0 = X-tilde, s = 1, A' = U_0) lies in C: its
+    projection is itself, so d_0 = sqrt(eps), the loss vanishes on the
+    observed entries, and F_0 = mu sum_e w_e ||x~_i - x~_j|| + rho sqrt(eps);
+    at mu = 0 that is rho sqrt(eps)."""
+    import math
+    X, M, E, w = mixture_problem(17, n=15, p=3, missing=0.2)
+    prob = mm.Problem(X, M, E, w)
+    Xt = prob.Xt
+    for mu in (0.0, 0.7, 3.0):
+        rho, eps = prob.constants(mu, mm.Opts())
+        _, dg = prob.iterate(mu, rho, eps, prob.initial_state(), "exact")
+        pen = math.fsum(w[e] * math.sqrt(math.fsum((Xt[E[e, 0], f] - Xt[E[e, 1], f]) ** 2 for f in range(3)))
+                        for e in range(len(E)))
+        assert dg["d"] == pytest.approx(math.sqrt(eps), rel=1e-12)
+        assert dg["F"] == pytest.approx(mu * pen + rho * math.sqrt(eps), rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_objective_value_two_points(seed):
+    """n = 2, one edge.  The projection keeps the mean of the two rows and
+    sets beta = a_1 - a_2 to the minimiser of ||delta - beta||^2/2 +
+    ||v - beta||^2, delta = u_1 - u_2, i.e. beta = (delta + 2 v)/3; so
+    dist^2 = ||delta - v||^2 / 3 with v = s (a'_1 - a'_2), and
+    F = 1/2 ||X - U||^2 + mu w ||v|| + rho sqrt(||delta - v||^2/3 + eps)."""
+    import math
+    rng = np.random.default_rng(300 + seed)
+    p = 4
+    X = rng.normal(size=(2, p))
+    E = np.array([[0, 1]])
+    w = np.array([rng.uniform(0.2, 2.0)])
+    prob = mm.Problem(X, None, E, w)
+    U, Ap = rng.normal(size=(2, p)), rng.normal(size=(2, p))
+    s = np.array([[0.0, 1.0, rng.uniform(0.05, 0.95), 0.5][seed]])
+    mu, rho, eps = rng.uniform(0.1, 3.0), rng.uniform(1.0, 5.0), rng.uniform(1e-4, 1e-1)
+    v = s[0] * (Ap[0] - Ap[1])
+    delta = U[0] - U[1]
+    d = math.sqrt(((delta - v) ** 2).sum() / 3.0 + eps)
+    F = 0.5 * ((X - U) ** 2).sum() + mu * w[0] * math.sqrt((v ** 2).sum()) + rho * d
+    for proj in ("exact", "gauss_seidel", "jacobi:200"):
+        _, dg = prob.iterate(mu, rho, eps, mm.State(U.copy(), s.copy(), Ap.copy()), proj)
+        assert dg["d"] == pytest.approx(d, rel=1e-12), proj
+        assert dg["F"] == pytest.approx(F, rel=1e-12), proj
+
+
 def test_stopping_rule_semantics():
     X, M, E, w = mixture_problem(13)
     prob = mm.Problem(X, M, E, w)
