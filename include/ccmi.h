@@ -97,7 +97,14 @@ typedef struct cc_server *cc_server_t;
  *               initial state U = A = X-tilde, V = D X-tilde.
  *   record_objective  1: keep the objective of every iteration
  *               (cc_get_trace).
- *   test_every  the window K of the stopping test, >= 1 (default 64). */
+ *   test_every  the window K of the stopping test, >= 1 (default 64).
+ *   proj_sweeps Jacobi sweeps of the paper's block update per MM iteration
+ *               (block-descent projection: the u_i are updated until they
+ *               stabilise), 1..64, each started from the previous sweep and
+ *               the first from the previous projection A'; default 1.  Any
+ *               count has the fixed points of the exact projection; more
+ *               sweeps bring each iteration's projection closer to it.
+ *               Batched and served solves take 1. */
 typedef struct {
   int32_t struct_size; /* sizeof(cc_solve_opts) */
   double eta;          /* default 1e-2 */
@@ -109,6 +116,7 @@ typedef struct {
   int32_t warm_start;  /* default 1 */
   int32_t record_objective; /* default 0 */
   int32_t test_every;  /* default 64 */
+  int32_t proj_sweeps; /* default 1 */
 } cc_solve_opts;
 
 /* Result of one solve (one mu).  objective and d belong to the last MM
@@ -168,22 +176,31 @@ cc_status cc_problem_dims(cc_problem_t prob, int64_t *n, int64_t *p,
 /* ---------------------------------------------------------------------
  * Solving
  * ---------------------------------------------------------------------
- * cc_solve: run the MM iteration at mu = gamma >= 0 until the stopping test
- * passes or max_iter iterations are done.  opts may be NULL (defaults).
- * info (host, may be NULL) is filled synchronously.  Afterwards the state
- * holds U, the factored V and the fusion pattern of the final iterate.
- * Returns CC_ERR_NUMERIC if d or the objective became non-finite. */
+ * cc_solve: run the MM iteration of Section "The Proximal Distance
+ * Algorithm" (projection, smoothed distance d, V update, U update with the
+ * missing-data majorisation of Section "Missing Data") at mu = gamma >= 0
+ * until the stopping test passes or max_iter iterations are done.  opts may
+ * be NULL (defaults).  info (host, may be NULL) is filled synchronously.
+ * Afterwards the state holds U, the factored V and the fusion pattern of the
+ * final iterate.  Returns CC_ERR_NUMERIC if d or the objective became
+ * non-finite (an ordinary status: the kernels run to their end); the state
+ * is then invalid, and the next warm-started solve starts from the initial
+ * state (cc_reset_state and cc_set_state restore one explicitly).  Argument
+ * errors (CC_ERR_INVALID_ARG) leave the state untouched. */
 cc_status cc_solve(cc_problem_t prob, double gamma, const cc_solve_opts *opts,
                    cc_solve_info *info);
 
-/* cc_solve_path: solve for gammas[0..n_gamma-1] (host) in the given order,
- * each warm-started from the previous one's final state (the first one
+/* cc_solve_path: the solution path over the regularisation parameter
+ * (Section "Evaluation of Clusters": one set of centres per mu, clusters
+ * read off as mu grows).  Solves gammas[0..n_gamma-1] (host) in the given
+ * order, each warm-started from the previous one's final state (the first one
  * from the current state if opts->warm_start, else from the initial state).
  * labels (device int32, n_gamma*n, may be NULL): row g holds the cluster
  * label of every case after gammas[g], the smallest case index of its
  * cluster.  U_path (device float32, n_gamma rows of n*p, row-major with
  * leading dimension p, may be NULL): the centres after each gamma.
- * infos (host, n_gamma entries, may be NULL). */
+ * infos (host, n_gamma entries, may be NULL).  Stops at the first gamma
+ * whose solve fails and returns its status (infos up to it are filled). */
 cc_status cc_solve_path(cc_problem_t prob, int32_t n_gamma,
                         const double *gammas, const cc_solve_opts *opts,
                         int32_t *labels, float *U_path, cc_solve_info *infos);
@@ -191,15 +208,22 @@ cc_status cc_solve_path(cc_problem_t prob, int32_t n_gamma,
 /* ---------------------------------------------------------------------
  * Results
  * --------------------------------------------------------------------- */
-/* Centres U of the current state into device memory of out_dtype, n rows of
- * ldu elements. */
+/* Centres U of the current state (the last MM iterate U_{m+1}; the
+ * minimiser of f_mu is approximated O(eta) closely, Section "The Proximal
+ * Distance Algorithm") into device memory of out_dtype, n rows of ldu
+ * elements.  Asynchronous on the problem's stream. */
 cc_status cc_get_U(cc_problem_t prob, int32_t out_dtype, void *U, int64_t ldu);
 /* Cluster labels (device int32, n): connected components of the fused edges
- * (v_e = 0 after the last V update), each labelled by its smallest case
- * index.  n_clusters (host, may be NULL) receives the count. */
+ * (v_e = 0 after the last V update: the group soft-threshold of the V
+ * update sets v_e exactly to zero when ||b_e|| <= mu w_e d / rho, and the
+ * paper reads clusters off the centres that have merged), each labelled by
+ * its smallest case index.  n_clusters (host, may be NULL) receives the
+ * count and makes the call synchronous. */
 cc_status cc_get_labels(cc_problem_t prob, int32_t *labels,
                         int32_t *n_clusters);
-/* Fused flag per input edge, in input order (device uint8, n_edges). */
+/* Fused flag per input edge, in input order (device uint8, n_edges): 1 when
+ * the V update's shrinkage set v_e to zero (fusion of the centres of its two
+ * cases), else 0.  Asynchronous on the problem's stream. */
 cc_status cc_get_fused_edges(cc_problem_t prob, uint8_t *fused);
 /* Objective of every iteration of the last solve with record_objective = 1
  * (host float64, up to cap values); *count receives the number stored. */
@@ -222,7 +246,11 @@ cc_status cc_kernel_stats(cc_problem_t prob, double *avg_ms, int64_t *launches);
 /* ---------------------------------------------------------------------
  * State checkpoint (warm starts across processes or problems)
  * ---------------------------------------------------------------------
- * The state is (U, s, A'), with V = diag(s) D A'.  cc_state_size gives the
+ * The state of the MM iteration is (U, V) (Section "The Proximal Distance
+ * Algorithm"); V is kept factored as V = diag(s) D A', A' the projection it
+ * was shrunk from, so the state is (U, s, A').  Warm starts along the path
+ * (Section "Evaluation of Clusters") carry it from one mu to the next; a
+ * checkpoint carries it across processes.  cc_state_size gives the
  * byte size of the serialised state; export writes it to host memory,
  * import reads it back into a problem of the same n, p, edge set and
  * precision (CC_ERR_INVALID_ARG otherwise).  cc_reset_state returns to the
@@ -362,7 +390,11 @@ cc_status cc_batch_destroy(cc_batch_t batch);
  * seconds = admission to done) as cc_solve_path gives them, and U (device
  * float32, n rows of p, may be NULL): the centres at the end of the path.
  * cc_server_release: frees a request that is not running (its budget share
- * returns).  cc_server_destroy frees every request. */
+ * returns).  cc_server_memory (host outputs, may be NULL): the device bytes
+ * counted against the budget by the admitted and finished requests not yet
+ * released, and the budget.  A request whose admission failed (state
+ * CC_REQ_FAILED, its status from cc_server_result) holds no device memory
+ * and is not counted.  cc_server_destroy frees every request. */
 #define CC_REQ_WAITING 0
 #define CC_REQ_ACTIVE 1
 #define CC_REQ_DONE 2
@@ -381,6 +413,7 @@ cc_status cc_server_status(cc_server_t server, int64_t ticket, int32_t *state,
 cc_status cc_server_result(cc_server_t server, int64_t ticket, int32_t *labels,
                            cc_solve_info *infos, float *U);
 cc_status cc_server_release(cc_server_t server, int64_t ticket);
+cc_status cc_server_memory(cc_server_t server, int64_t *used, int64_t *budget);
 cc_status cc_server_destroy(cc_server_t server);
 
 /* ---------------------------------------------------------------------

@@ -32,6 +32,7 @@ class SolveOpts(C.Structure):
         ("warm_start", i32),
         ("record_objective", i32),
         ("test_every", i32),
+        ("proj_sweeps", i32),
     ]
 
 
@@ -96,6 +97,7 @@ SIGNATURES = {
     "cc_server_status": (i32, [vp, i64, P_i32, P_f64, P_f64, P_f64]),
     "cc_server_result": (i32, [vp, i64, vp, C.POINTER(SolveInfo), vp]),
     "cc_server_release": (i32, [vp, i64]),
+    "cc_server_memory": (i32, [vp, P_i64, P_i64]),
     "cc_server_destroy": (i32, [vp]),
 }
 

@@ -423,6 +423,12 @@ class Server:
         check(_lib.load().cc_server_release(self._h, ticket))
         self._shape.pop(ticket, None)
 
+    def memory(self):
+        """(device bytes counted against the budget, the budget)."""
+        used, budget = C.c_int64(), C.c_int64()
+        check(_lib.load().cc_server_memory(self._h, C.byref(used), C.byref(budget)))
+        return used.value, budget.value
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.load().cc_server_destroy(self._h)

@@ -90,6 +90,7 @@ void cc_default_opts(cc_solve_opts *o) {
   o->warm_start = 1;
   o->record_objective = 0;
   o->test_every = 64;
+  o->proj_sweeps = 1;
 }
 
 cc_status cc_problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
@@ -310,6 +311,16 @@ cc_status cc_server_release(cc_server_t server, int64_t ticket) {
   Request *R = server_find(S, ticket);
   if (!R) { set_error("unknown ticket"); return CC_ERR_INVALID_ARG; }
   return server_release(S, R);
+  CC_GUARD_END
+}
+
+cc_status cc_server_memory(cc_server_t server, int64_t *used, int64_t *budget) {
+  CC_GUARD_BEGIN
+  if (!server) { set_error("server is NULL"); return CC_ERR_INVALID_ARG; }
+  const Server *S = reinterpret_cast<const Server *>(server);
+  if (used) *used = S->used;
+  if (budget) *budget = S->budget;
+  return CC_OK;
   CC_GUARD_END
 }
 

@@ -26,6 +26,7 @@ constexpr int kEdgeWaves = kEdgeBlock / kWave;
 constexpr int kEsumRows = 512;   // max partial rows the edge stage leaves
 constexpr int kEsumStride = 10;  // doubles per partial row (kIterSums, padded to 16 B)
 constexpr int kItemEdges = 8;    // edges per work item of the item edge sweep
+constexpr int kMaxProjSweeps = 64;  // Jacobi sweeps of the projection per MM iteration
 
 // Device-resident iteration scalars, in two slots.  Written by the host
 // only through the set-parameters and reset kernels.  A point sweep reads
@@ -103,6 +104,9 @@ struct Problem {
   int32_t *degE = nullptr, *colE = nullptr, *eidE = nullptr;
   double *qE = nullptr;     // q per ELL entry
   int32_t *epos = nullptr;  // ELL positions of (i->j) and (j->i) per edge
+  int psweeps = 1;          // projection sweeps per MM iteration (this solve)
+  double *H = nullptr;       // several sweeps: h_i = sum_j s_ij (a'_i - a'_j), n x ld FP64
+  void *T[2] = {nullptr, nullptr};  // several sweeps: gather copies of the sweeps' increments
   int slab_f = 0;           // > 0: LDS-slab point sweep with F-feature tiles
   bool ell_cm = false;      // ELL stored column-major (entry k of i at k*n + i)
   int cur_K = 64;
@@ -229,6 +233,7 @@ struct Request {
   std::vector<double> gammas, rho, eps, thr;
   Problem *P = nullptr;            // owned once admitted
   int64_t footprint = 0;           // bytes counted against the budget
+  bool charged = false;            // footprint counted in the server's used bytes
   BatchInst *bi = nullptr;         // device descriptor and its arrays
   double *gconst = nullptr;
   uint8_t *fused = nullptr;
@@ -237,6 +242,7 @@ struct Request {
   std::vector<double> hinfo;       // per-gamma info once done
   double t_submit = 0, t_admit = 0, t_done = 0;  // seconds since server creation
   int status = 0;
+  std::string error;               // message of a failed admission
 };
 
 struct Server {

@@ -45,6 +45,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <type_traits>
 
 #include "ccmi_internal.h"
 
@@ -341,6 +342,9 @@ struct PointArgs {
   const DevScalars *sin;  // scalars of the previous iteration
   DevScalars *sout;       // advanced scalars (block 0 writes)
   const BatchInst *bi;    // batched solves only (else null)
+  // several projection sweeps per MM iteration (k_point_rhs only)
+  double *H;              // h_i = sum_j s_ij (a'_i - a'_j), FP64
+  void *T0;               // gather copy of the first sweep's increment A - A'
 };
 
 // Per-edge bookkeeping shared by the fused edge kernel and the reduction
@@ -517,7 +521,11 @@ __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, co
 }
 
 // ------------------------------------------------------------- k_point
-template <int PREC, int VEC, bool PF, bool BATCH>
+// JAC: the first of several Jacobi sweeps of the projection.  It stores the
+// first sweep's A (the state type), a gather copy of its increment A - A'
+// (T0) and h_i (FP64, H); k_jacobi runs the other sweeps and the terms of d
+// that involve the final A (||U - A||^2, the A window and sum_i <h_i, a_i>).
+template <int PREC, int VEC, bool PF, bool BATCH, bool JAC = false>
 __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   using TS = typename Traits<PREC>::TS;
   using TG = typename Traits<PREC>::TG;
@@ -729,7 +737,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
       }
       const double inv1d = 1.0 / (1.0 + (double)deg);
       const double S = (double)deg - C;
-      double u[VEC], an[VEC], gn[VEC];
+      double u[VEC], an[VEC], gn[VEC], rr[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         double uu;
@@ -746,20 +754,34 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
         anew = round_to<TS>(anew);
         const double g = round_to<TG>(anew);
         u[v] = uu; an[v] = anew; gn[v] = g;
-        const double dua = uu - anew;
-        ps[0] = fma(dua, dua, ps[0]);
+        if constexpr (JAC) {
+          rr[v] = h;
+          gn[v] = round_to<TG>(anew - ap[v]);
+        } else {
+          const double dua = uu - anew;
+          ps[0] = fma(dua, dua, ps[0]);
+          ps[5] = fma(h, g, ps[5]);
+        }
         if (mk[v]) { const double r = x[v] - uu; ps[3] = fma(r, r, ps[3]); }
         ps[4] = fma(uu, uu, ps[4]);
-        ps[5] = fma(h, g, ps[5]);
       }
-      if constexpr (PF && VEC == 4) {
+      if constexpr (JAC) {
+        VecIO<VEC>::store(U + row, u);
+        VecIO<VEC>::store(An + row, an);
+        VecIO<VEC>::store(a.H + row, rr);
+        VecIO<VEC>::store(reinterpret_cast<TG *>(a.T0) + row, gn);
+      } else if constexpr (PF && VEC == 4) {
+        // U and, with an FP32 gather copy, A are streaming rows; where A is
+        // itself what the next sweep gathers (no copy) it keeps ordinary
+        // stores, so that it stays cached for those gathers
         NtIO<TS, 4>::store(U + row, u);
-        NtIO<TS, 4>::store(An + row, an);
+        if constexpr (Traits<PREC>::mirror) NtIO<TS, 4>::store(An + row, an);
+        else VecIO<VEC>::store(An + row, an);
       } else {
         VecIO<VEC>::store(U + row, u);
         VecIO<VEC>::store(An + row, an);
       }
-      if (Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, gn);
+      if (!JAC && Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, gn);
       if (winU) {
         double us[VEC];
         VecIO<VEC>::load(Us + row, us);
@@ -768,7 +790,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
       }
       if (snapU0 || winU) VecIO<VEC>::store(Us + row, u);
       if (initA) VecIO<VEC>::store(As + row, ap);
-      if (winA) {
+      if (!JAC && winA) {
         double prev[VEC];
         if (m == 0) {
 #pragma unroll
@@ -793,6 +815,12 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
 template <int PREC, int VEC, bool PF>
 __global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
   point_sweep<PREC, VEC, PF, false>(a, hw_blk());
+}
+
+// First sweep of several (proj_sweeps > 1): the same launch as k_point.
+template <int PREC, int VEC, bool PF>
+__global__ __launch_bounds__(kPointBlock) void k_point_rhs(PointArgs a) {
+  point_sweep<PREC, VEC, PF, false, true>(a, hw_blk());
 }
 
 // Batched: block q works for instance tab[q].x as its local block tab[q].y.
@@ -962,6 +990,164 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < kPointSums; ++q) a.psum[(size_t)lb * 8 + q] = ps[q];
+  }
+}
+
+// ------------------------------------------------------------- k_jacobi
+// Projection sweeps 2..K of an MM iteration (proj_sweeps = K > 1).  The
+// block update of the projection, with V fixed for the iteration, reads
+//   a_i <- (u_i + h_i + sum_{j in N_i} a_j) / (1 + |N_i|),
+// h_i = sum_j s_ij (a'_i - a'_j) from the projection A' the current V was
+// shrunk from.  Between two sweeps only the neighbour sum changes, so sweep
+// k+1 adds to a_i the mean increment of its neighbours,
+//   a_i^{k+1} = a_i^k + sum_j delta_j^k / (1 + |N_i|),  delta^k = a^k - a^{k-1},
+// which equals the block update exactly; gathering the increments (small
+// near the fixed point) instead of the values keeps the rounding of an FP32
+// gather copy at the scale of the increment.  k_point_rhs stored the first
+// sweep's A, its increment over A' and h.  One wave per (point, feature
+// tile) item, on the grid and item split of the point sweep, so that block
+// lb of the last sweep completes row lb of the point-sweep partials:
+// ||U - A||^2 (entry 0), the A window (entry 1) and sum_i <h_i, a_i>
+// (entry 5) of the final A.  Each sweep updates A in place (a point reads
+// only its own row of A; neighbours are read through the increments); the
+// last one also writes the gather copy of A that the edge stage and the
+// next iteration read.
+struct JacArgs {
+  int n, ld, nitems, chunk, ell_s, K;
+  const int32_t *colE;
+  const double *H;    // h per point-feature, FP64
+  const void *Din;    // gather copy of the previous sweep's increment
+  void *Dout;         // intermediate sweeps: this sweep's increment
+  const void *U;      // last sweep: U_m
+  void *A0, *A1, *G0, *G1, *Asnap;
+  double *psum;
+  const DevScalars *sc;  // scalars of the iteration in progress
+};
+
+template <int PREC, int VEC, bool LAST>
+__global__ __launch_bounds__(kPointBlock) void k_jacobi(JacArgs a) {
+  using TS = typename Traits<PREC>::TS;
+  using TG = typename Traits<PREC>::TG;
+  __shared__ double scratch[kPointWaves * 3];
+  const DevScalars *sc = a.sc;
+  if (sc->done) return;
+  const int m = sc->m, pa = sc->pa;
+  const bool winA = (m % a.K) == (a.K - 1);
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const Blk blk = hw_blk();
+  const int lb = blk.lb;
+  const int it0 = lb * a.chunk, it1 = min(it0 + a.chunk, a.nitems);
+  const int W = kWave * VEC;
+  const TG *Di = reinterpret_cast<const TG *>(a.Din);
+  TG *Do = reinterpret_cast<TG *>(a.Dout);
+  TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
+  TS *An = reinterpret_cast<TS *>(pa == 0 ? a.A1 : a.A0);
+  const TS *Ap = reinterpret_cast<const TS *>(pa == 0 ? a.A0 : a.A1);
+  const TS *U = reinterpret_cast<const TS *>(a.U);
+  TS *As = reinterpret_cast<TS *>(a.Asnap);
+  double ps[3] = {0.0, 0.0, 0.0};
+  for (int item = it0 + wave; item < it1; item += kPointWaves) {
+    const int t = item / a.n, i = item - t * a.n;
+    const int f0 = t * W + lane * VEC;
+    const bool active = f0 < a.ld;
+    // lanes past the row end load feature 0 of the same rows and drop it
+    const int f0c = active ? f0 : 0;
+    const size_t row = (size_t)i * a.ld + f0;
+    const size_t rowc = (size_t)i * a.ld + f0c;
+    const size_t rs = (size_t)i * a.ell_s;
+    TS akr[VEC];
+    RawIO<TS, VEC>::load(An + rowc, akr);
+    double hr[VEC];
+    TS ur[VEC];
+    if constexpr (LAST) {
+      RawIO<double, VEC>::load(a.H + rowc, hr);
+      RawIO<TS, VEC>::load(U + rowc, ur);
+    }
+    double sum[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) sum[v] = 0.0;
+    int deg = 0;
+    // neighbour slots in chunks of 64 (unused slots hold -1 after the used
+    // ones); rows gathered in batches of 8, the next batch issued before the
+    // current one is added; a slot past the count reads row i with weight 0
+    for (int k64 = 0; k64 < a.ell_s; k64 += kWave) {
+      int jl = -1;
+      if (lane < a.ell_s - k64) jl = a.colE[rs + k64 + lane];
+      const int cnt = __popcll(__ballot(jl >= 0));
+      auto issue = [&](int k0, TG (&r)[8][VEC], double (&wt)[8]) {
+        int j[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const bool ok = k0 + q < cnt;
+          j[q] = ok ? __builtin_amdgcn_readlane(jl, k0 + q) : i;
+          wt[q] = ok ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) RawIO<TG, VEC>::load(Di + (size_t)j[q] * a.ld + f0c, r[q]);
+      };
+      auto consume = [&](const TG (&r)[8][VEC], const double (&wt)[8]) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) sum[v] = fma(wt[q], (double)r[q][v], sum[v]);
+        }
+      };
+      const int nbat = (cnt + 7) >> 3;
+      TG ra[8][VEC], rb[8][VEC];
+      double wa[8], wb[8];
+      if (nbat > 0) {
+        issue(0, ra, wa);
+        for (int b = 0;; b += 2) {
+          issue(8 * (b + 1), rb, wb);
+          consume(ra, wa);
+          if (b + 1 >= nbat) break;
+          issue(8 * (b + 2), ra, wa);
+          consume(rb, wb);
+          if (b + 2 >= nbat) break;
+        }
+      }
+      deg += cnt;
+      if (cnt < kWave) break;
+    }
+    if (active) {
+      const double inv1d = 1.0 / (1.0 + (double)deg);
+      double an[VEC], dn[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const double inc = sum[v] * inv1d;
+        an[v] = round_to<TS>((double)akr[v] + inc);
+        dn[v] = round_to<TG>(LAST ? an[v] : inc);
+      }
+      VecIO<VEC>::store(An + row, an);
+      if constexpr (LAST) {
+        if (Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, dn);
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const double dua = (double)ur[v] - an[v];
+          ps[0] = fma(dua, dua, ps[0]);
+          ps[2] = fma(hr[v], dn[v], ps[2]);
+        }
+        if (winA) {
+          double prev[VEC];
+          if (m == 0) VecIO<VEC>::load(Ap + row, prev);
+          else VecIO<VEC>::load(As + row, prev);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) { const double da = an[v] - prev[v]; ps[1] = fma(da, da, ps[1]); }
+          VecIO<VEC>::store(As + row, an);
+        }
+      } else {
+        VecIO<VEC>::store(Do + row, dn);
+      }
+    }
+  }
+  if constexpr (LAST) {
+    block_sum<3>(ps, scratch);
+    if (threadIdx.x == 0) {
+      a.psum[(size_t)lb * 8 + 0] = ps[0];
+      a.psum[(size_t)lb * 8 + 1] = ps[1];
+      a.psum[(size_t)lb * 8 + 5] = ps[2];
+    }
   }
 }
 
@@ -1647,11 +1833,40 @@ static PointArgs point_args(Problem *P, const Launch &Lp) {
   return PointArgs{(int)P->n, (int)P->ld, P->ntile, Lp.nitems, Lp.chunk,
                    P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
                    P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_K, Lp.blocks,
-                   P->psum, P->esum, P->nbe, P->trace, P->sc + P->slot, P->sc + (P->slot ^ 1), nullptr};
+                   P->psum, P->esum, P->nbe, P->trace, P->sc + P->slot, P->sc + (P->slot ^ 1), nullptr,
+                   P->H, P->T[0]};
+}
+
+// Projection sweeps 2..K after k_point_rhs (scalars: the slot the point
+// sweep wrote).  Sweep k reads the increments of sweep k-1: T[0] holds the
+// first sweep's, then T[0] and T[1] alternate; the last writes the gather
+// copy of the state's A.
+template <int PREC, int VEC>
+static void launch_jacobi_t(Problem *P, const Launch &Lp) {
+  JacArgs ja{(int)P->n, (int)P->ld, Lp.nitems, Lp.chunk, P->ell_s, P->cur_K, P->colE, P->H,
+             nullptr, nullptr, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Asnap, P->psum,
+             P->sc + P->slot};
+  for (int k = 2; k <= P->psweeps; ++k) {
+    ja.Din = P->T[(k - 2) % 2];
+    ja.Dout = P->T[(k - 1) % 2];
+    if (k < P->psweeps)
+      klaunch(k_jacobi<PREC, VEC, false>, dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream, nullptr, nullptr, ja);
+    else
+      klaunch(k_jacobi<PREC, VEC, true>, dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream, nullptr, nullptr, ja);
+  }
 }
 
 template <int PREC, int VEC>
 static void launch_point_t(Problem *P, const Launch &Lp) {
+  if (P->psweeps > 1) {
+    if (Lp.chunk > kPointWaves)
+      klaunch(k_point_rhs<PREC, VEC, true>, dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream, P->pev[0], P->pev[1],
+              point_args(P, Lp));
+    else
+      klaunch(k_point_rhs<PREC, VEC, false>, dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream, P->pev[0], P->pev[1],
+              point_args(P, Lp));
+    return;
+  }
   // prefetching pays when a wave has more than one item
   if (Lp.chunk > kPointWaves)
     klaunch(k_point<PREC, VEC, true>, dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream, P->pev[0], P->pev[1],
@@ -1811,6 +2026,19 @@ static void launch_iteration(Problem *P) {
   else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
   else launch_point_p<kMixed>(P, Lp);
   P->slot ^= 1;
+  if (P->psweeps > 1) {
+    auto jac = [&](auto prec_tag) {
+      constexpr int PR = decltype(prec_tag)::value;
+      switch (P->vec) {
+        case 1: launch_jacobi_t<PR, 1>(P, Lp); break;
+        case 2: launch_jacobi_t<PR, 2>(P, Lp); break;
+        default: launch_jacobi_t<PR, 4>(P, Lp); break;
+      }
+    };
+    if (P->precision == kF32) jac(std::integral_constant<int, kF32>());
+    else if (P->precision == kF64) jac(std::integral_constant<int, kF64>());
+    else jac(std::integral_constant<int, kMixed>());
+  }
   if (P->precision == kF32) launch_edge_p<kF32>(P, 0, nbp);
   else if (P->precision == kF64) launch_edge_p<kF64>(P, 0, nbp);
   else launch_edge_p<kMixed>(P, 0, nbp);
@@ -1856,7 +2084,7 @@ void problem_free(Problem *P) {
                   P->itemI, P->itemJ, P->itemE,
                   P->ei, P->ej, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qE, P->epos, P->degE, P->colE,
                   P->eidE, P->part, P->psum,
-                  P->esum, P->trace, P->sc, P->ncl_dev};
+                  P->esum, P->trace, P->sc, P->ncl_dev, P->H, P->T[0], P->T[1]};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (Traits<kMixed>::mirror && P->precision == kMixed) {
@@ -2250,6 +2478,21 @@ cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info 
   if (o.test_every < 1) { set_error("test_every must be >= 1"); return CC_ERR_INVALID_ARG; }
   if (!(o.tol >= 0.0)) { set_error("tol must be >= 0"); return CC_ERR_INVALID_ARG; }
   if (!(o.eta > 0.0) && !(o.eps > 0.0)) { set_error("need eta > 0 or eps > 0"); return CC_ERR_INVALID_ARG; }
+  if (o.proj_sweeps < 1 || o.proj_sweeps > kMaxProjSweeps) {
+    set_error("proj_sweeps must be in 1.." + std::to_string(kMaxProjSweeps));
+    return CC_ERR_INVALID_ARG;
+  }
+  if (o.proj_sweeps > 1 && P->slab_f > 0) {
+    set_error("proj_sweeps > 1 needs the wave point sweep (not the LDS-slab option)");
+    return CC_ERR_INVALID_ARG;
+  }
+  if (o.proj_sweeps > 1 && !P->H) {
+    const size_t nl = (size_t)P->n * P->ld;
+    CC_TRY(dmalloc((void **)&P->H, nl * 8));
+    CC_TRY(dmalloc(&P->T[0], nl * tg_size(P->precision)));
+    CC_TRY(dmalloc(&P->T[1], nl * tg_size(P->precision)));
+  }
+  P->psweeps = o.proj_sweeps;
   const auto t0 = std::chrono::steady_clock::now();
   if (!o.warm_start || !P->state_valid) CC_TRY(reset_state(P));
   double rho, eps, thr;
@@ -2620,6 +2863,7 @@ static int tune_vec(int c) { return 1 << (c / 3); }
 static int tune_ipw(int c) { return c % 3 == 0 ? 1 : (c % 3 == 1 ? 4 : 16); }
 
 static cc_status check_opts(const cc_solve_opts &o) {
+  if (o.proj_sweeps != 1) { set_error("batched and served solves run one projection sweep per MM iteration (proj_sweeps = 1)"); return CC_ERR_INVALID_ARG; }
   if (o.max_iter < 1) { set_error("max_iter must be >= 1"); return CC_ERR_INVALID_ARG; }
   if (o.test_every < 1) { set_error("test_every must be >= 1"); return CC_ERR_INVALID_ARG; }
   if (!(o.tol >= 0.0)) { set_error("tol must be >= 0"); return CC_ERR_INVALID_ARG; }
@@ -2922,13 +3166,12 @@ static int64_t request_bytes(int64_t n, int64_t p, int32_t k, bool mask, int pre
          n_gamma * kInfoVals * 8 + (int64_t)kMaxBlocks * 64;
 }
 
+static void free_request_device(Request *R);
+
 void server_free(Server *S) {
   if (!S) return;
   for (Request *R : S->all) {
-    if (R->P) problem_free(R->P);
-    void *bufs[] = {R->bi, R->gconst, R->fused, R->info, R->tdone};
-    for (void *b : bufs)
-      if (b) (void)hipFree(b);
+    free_request_device(R);
     delete R;
   }
   free_launch_set(S->ls);
@@ -2994,6 +3237,20 @@ cc_status server_submit(Server *S, int64_t n, int64_t p, const float *X, const u
   S->all.push_back(R);
   if (ticket) *ticket = R->ticket;
   return CC_OK;
+}
+
+// Device memory of a request (problem, descriptor, per-gamma outputs).
+static void free_request_device(Request *R) {
+  if (R->P) problem_free(R->P);
+  R->P = nullptr;
+  void *bufs[] = {R->bi, R->gconst, R->fused, R->info, R->tdone};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  R->bi = nullptr;
+  R->gconst = nullptr;
+  R->fused = nullptr;
+  R->info = nullptr;
+  R->tdone = nullptr;
 }
 
 // Weights, problem and device descriptor of a request; its host copies go.
@@ -3065,12 +3322,16 @@ cc_status server_step(Server *S, int32_t *n_active, int32_t *n_waiting, int32_t 
     S->waiting.erase(S->waiting.begin());
     cc_status st = admit(S, R);
     if (st != CC_OK) {
+      // a failed admission keeps no device memory and is never charged
+      R->error = cc_last_error_message();
+      free_request_device(R);
       R->state = CC_REQ_FAILED;
       R->status = st;
       R->t_done = host_seconds() - S->t0;
       continue;
     }
     S->used += R->footprint;
+    R->charged = true;
     S->active.push_back(R);
     S->dirty = true;
   }
@@ -3135,6 +3396,7 @@ Request *server_find(Server *S, int64_t ticket) {
 }
 
 cc_status server_result(Server *S, Request *R, int32_t *labels, cc_solve_info *infos) {
+  if (R->state == CC_REQ_FAILED) { set_error("admission failed: " + R->error); return (cc_status)R->status; }
   if (R->state != CC_REQ_DONE) { set_error("request not done"); return CC_ERR_STATE; }
   Problem *P = R->P;
   const int ng = (int)R->gammas.size();
@@ -3171,15 +3433,12 @@ cc_status server_result(Server *S, Request *R, int32_t *labels, cc_solve_info *i
 
 cc_status server_release(Server *S, Request *R) {
   if (R->state == CC_REQ_ACTIVE) { set_error("request still running"); return CC_ERR_STATE; }
-  if (R->state == CC_REQ_WAITING) {
-    S->waiting.erase(std::find(S->waiting.begin(), S->waiting.end(), R));
-  } else if (R->P) {
+  if (R->state == CC_REQ_WAITING) S->waiting.erase(std::find(S->waiting.begin(), S->waiting.end(), R));
+  if (R->charged) {
     S->used -= R->footprint;
+    R->charged = false;
   }
-  if (R->P) problem_free(R->P);
-  void *bufs[] = {R->bi, R->gconst, R->fused, R->info, R->tdone};
-  for (void *b : bufs)
-    if (b) (void)hipFree(b);
+  free_request_device(R);
   S->all.erase(std::find(S->all.begin(), S->all.end(), R));
   delete R;
   return CC_OK;

@@ -344,3 +344,130 @@ def test_small_eta_mixed_converged(cc, gamma):
     assert np.array_equal(fused, info.fused)
     assert np.array_equal(lab.cpu().numpy(), info.labels)
     assert ncl == info.n_clusters
+
+
+# ------------------------------------- several projection sweeps per iteration
+# proj_sweeps = K runs K Jacobi sweeps of the paper's block update per MM
+# iteration (the block-descent projection repeated towards stability), the
+# first from the previous projection; the oracle's "jacobi:K" does the same.
+@pytest.mark.parametrize("K,iters", [(2, 7), (2, 60), (4, 60), (3, 61)])
+def test_proj_sweeps_f64_match_oracle_trajectory(cc, K, iters):
+    X, M, E, w = plain_problem()
+    st, info = oracle_jacobi(X, M, E, w).solve(
+        10.0, mm.Opts(tol=0, max_iter=iters, proj=f"jacobi:{K}", record=True, test_every=4))
+    with _gpu(cc, X, M, E, w, "f64") as g:
+        gi = g.solve(10.0, tol=0.0, max_iter=iters, record_objective=1, proj_sweeps=K, test_every=4)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+        F = g.trace()
+    assert gi["iters"] == iters
+    assert rel_max(U, st.U) < 1e-11
+    assert rel_max(A, st.A) < 1e-11
+    assert np.abs(s - st.s).max() < 1e-9
+    assert np.array_equal(s == 0, st.s == 0)
+    assert np.allclose(F, info.trace_F, rtol=1e-10, atol=0)
+    assert gi["d"] == pytest.approx(info.d, rel=1e-10)
+
+
+@pytest.mark.parametrize("vec", ["1", "2", "4"])
+def test_proj_sweeps_tiles_and_missing_data(cc, vec, monkeypatch):
+    """Two and five sweeps on a masked problem whose rows span several
+    feature tiles (the last ragged) at every tile width; the window of the
+    stopping test (K = 1) makes the last sweep compare with the previous
+    projection itself."""
+    monkeypatch.setenv("CCMI_VEC", vec)
+    X, M, E, w, _ = reduced_expression(n=300, p=150)
+    for K, win in ((2, 1), (5, 64)):
+        st, info = oracle_jacobi(X, M, E, w).solve(
+            3.0, mm.Opts(tol=0, max_iter=70, proj=f"jacobi:{K}", test_every=win))
+        with _gpu(cc, X, M, E, w, "f64") as g:
+            gi = g.solve(3.0, tol=0.0, max_iter=70, proj_sweeps=K, test_every=win)
+            U, A, s = (t.cpu().numpy() for t in g.get_state())
+        assert rel_max(U, st.U) < 1e-11, K
+        assert rel_max(A, st.A) < 1e-11, K
+        assert gi["rel_change"] == pytest.approx(info.rel_change, rel=1e-8), K
+
+
+def test_proj_sweeps_prefetch_and_mixed(cc):
+    """Several items per wave (3000 points x 3 tiles) with three sweeps:
+    FP64 to rounding, the mixed precision within its fixed-iteration bar."""
+    X, M, E, w, _ = reduced_expression(n=3000, p=700)
+    st, _ = oracle_jacobi(X, M, E, w).solve(5.0, mm.Opts(tol=0, max_iter=12, proj="jacobi:3"))
+    for precision, tol in (("f64", 1e-11), ("mixed", 2e-6)):
+        with _gpu(cc, X, M, E, w, precision) as g:
+            g.solve(5.0, tol=0.0, max_iter=12, proj_sweeps=3)
+            U, A, s = (t.cpu().numpy() for t in g.get_state())
+        assert rel_max(U, st.U) < tol, precision
+        assert rel_max(A, st.A) < tol, precision
+
+
+@pytest.mark.parametrize("K", [2, 4])
+def test_proj_sweeps_mixed_converged(cc, K):
+    """The converged mixed-precision solve with K sweeps reaches the
+    oracle's fixed point (that of the exact projection) within 1e-5, with
+    the same fused edges and labels."""
+    X, M, E, w = plain_problem()
+    X = as_f32_values(X)
+    st, info = oracle_jacobi(X, M, E, w).solve(10.0, mm.Opts(proj=f"jacobi:{K}"))
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        gi = g.solve(10.0, proj_sweeps=K)
+        U = g.U(torch.float64).cpu().numpy()
+        lab, ncl = g.labels()
+        fused = g.fused_edges().cpu().numpy().astype(bool)
+    assert gi["converged"] == 1 and info.converged
+    assert rel_max(U, st.U) <= 1e-5
+    assert np.array_equal(fused, info.fused)
+    assert np.array_equal(lab.cpu().numpy(), info.labels)
+
+
+def test_proj_sweeps_rejected_where_unsupported(cc):
+    X, M, E, w = plain_problem()
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        for bad in (0, 65):
+            with pytest.raises(cc.CCError) as ei:
+                g.solve(1.0, proj_sweeps=bad)
+            assert ei.value.status == 1
+        with pytest.raises(cc.CCError):
+            cc.Batch([g], [[1.0]], autotune=False, proj_sweeps=2)
+
+
+def test_f32_prefetch_path(cc):
+    """FP32 state with several items per wave (the point sweep's prefetching
+    form), where A is itself the array the next sweep gathers: trajectory
+    within the FP32 bar."""
+    X, M, E, w, _ = reduced_expression(n=3000, p=700)
+    st, _ = oracle_jacobi(X, M, E, w).solve(5.0, mm.Opts(tol=0, max_iter=12, proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, "f32") as g:
+        g.solve(5.0, tol=0.0, max_iter=12)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    assert rel_max(U, st.U) < 2e-5
+    assert rel_max(A, st.A) < 2e-5
+
+
+# ------------------------------------------------------------ numeric errors
+def test_non_finite_state_reports_numeric_error(cc):
+    """A state with a non-finite entry makes d non-finite: the solve returns
+    CC_ERR_NUMERIC (an ordinary status, no device fault), the next
+    warm-started solve starts again from the initial state, and after
+    cc_reset_state the problem solves as a fresh one does, bitwise."""
+    X, M, E, w = plain_problem()
+    X = as_f32_values(X)
+    with _gpu(cc, X, M, E, w, "mixed") as ref:
+        ref.solve(10.0, tol=0.0, max_iter=50)
+        Uref = ref.U(torch.float64).cpu().numpy()
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+        U[5, 3] = np.nan
+        g.set_state(U, A, s)
+        with pytest.raises(cc.CCError) as ei:
+            g.solve(10.0, max_iter=100)
+        assert ei.value.status == 4  # CC_ERR_NUMERIC
+        g.solve(10.0, tol=0.0, max_iter=50)  # warm start falls back to the initial state
+        assert np.array_equal(g.U(torch.float64).cpu().numpy(), Uref)
+        U[5, 3] = np.inf
+        g.set_state(U, A, s)
+        with pytest.raises(cc.CCError) as ei:
+            g.solve(10.0, max_iter=100)
+        assert ei.value.status == 4
+        g.reset_state()
+        g.solve(10.0, tol=0.0, max_iter=50)
+        assert np.array_equal(g.U(torch.float64).cpu().numpy(), Uref)
