@@ -96,3 +96,39 @@ def test_batch_rejects_bad_input(cc):
         cc.Batch([pr, pr64], [g, g], autotune=False)  # mixed precisions
     pr.close()
     pr64.close()
+
+
+def test_batched_instances_match_oracle(cc):
+    """Batched instances (in shared launches with others) against the FP64
+    oracle on the same edges and weights: every gamma the oracle's stopping
+    test passes is converged in the batch too, with the same labels and
+    iteration count within one test window; the centres after each gamma
+    (from the same instance solved alone, which the batch equals bitwise)
+    and after the path agree within 1e-5.  Both sides stop at tol 1e-4 or
+    5000 MM iterations per gamma (the batched benchmark's settings)."""
+    from oracle import mm
+    opts = dict(max_iter=5000, tol=1e-4)
+    ids = [14, 3, 24, 31, 2]
+    inst = []
+    for b in ids:
+        X, e, w, _ = instance(b)
+        inst.append((X, e, w, [float(g) for g in gen.batched_instance(b).gammas[::3]]))
+    probs = [make(cc, X, e, w) for X, e, w, _ in inst]
+    with cc.Batch(probs, [g for *_, g in inst], autotune=False, **opts) as bt:
+        labs, infos, _ = bt.run()
+    finals = [pr.get_state()[0].cpu().numpy() for pr in probs]
+    for pr in probs:
+        pr.close()
+    for b, (X, e, w, g) in enumerate(inst[:3]):
+        _, oinf, oU = mm.Problem(X, None, e, w).solve_path(g, mm.Opts(proj="jacobi:1", **opts))
+        with make(cc, X, e, w) as pr:
+            _, _, Up = pr.solve_path(g, labels=False, U_path=True, **opts)
+        Up = Up.cpu().numpy()
+        assert sum(i.converged for i in oinf) >= len(g) - 1
+        for k, oi in enumerate(oinf):
+            if oi.converged:
+                assert infos[b][k]["converged"] == 1, (ids[b], k)
+                assert abs(infos[b][k]["iters"] - oi.iters) <= mm.DEFAULT_TEST_EVERY, (ids[b], k)
+                assert np.array_equal(labs[b][k].cpu().numpy(), oi.labels), (ids[b], k)
+                assert rel_max(Up[k], oU[k]) < 1e-5, (ids[b], k)
+        assert rel_max(finals[b], oU[-1]) < 1e-5, ids[b]
