@@ -66,20 +66,35 @@ WORKLOAD_TEXT = {
 }
 
 
-def point_sweep_bytes(n, p, E, precision, has_mask):
-    """Algorithmic bytes of one point-sweep launch: every array element it
-    must touch counted once (neighbour rows are re-reads of the same array).
-    Per point-feature: X, mask, U write (and U read where entries are
-    missing: without a mask U_m follows from X and A_{m-1}), A' read, A
-    write, and for the mixed precision the FP32 copy of A' read and of A
-    written.  Per edge: the neighbour slots of both directions (16 B), the
-    previous norm, the weight and the written shrink factor (8 B each)."""
+def algorithmic_bytes(n, p, E, has_mask):
+    """Bytes the method itself must move per MM iteration with FP32 state,
+    each array element counted once (neighbour rows are re-reads of the same
+    array).  Point sweep (U update and the projection sweep) per
+    point-feature: X 4, the mask 1 (with missing data), U read 4 and write 4,
+    A' read 4, A write 4; per edge the neighbour slot and q factor of both
+    directions, 2 x (4 + 8) B.  Edge stage per point-feature: the rows of
+    the new A and of A' (4 + 4); per edge its ends, weight, shrink factor,
+    norms and q (about 60 B less the point sweep's 24).  Returns
+    (point-sweep bytes, whole-iteration bytes, point-sweep bytes per
+    point-feature)."""
+    k1 = 20 + (1 if has_mask else 0)
+    point = k1 * n * p + 24 * E
+    iteration = (k1 + 8) * n * p + 60 * E
+    return point, iteration, k1
+
+
+def implementation_bytes(n, p, E, precision, has_mask):
+    """Bytes one point-sweep launch of this implementation moves: with
+    missing data it reads U (else U_m follows from X and A'), and the mixed
+    precision keeps U and A in FP64 beside an FP32 gather copy of A (its own
+    row read, the new one written).  Same per-edge bytes as the algorithmic
+    count.  Returns (bytes per launch, bytes per point-feature)."""
     sx = 8 if precision == "f64" else 4
     ss = 4 if precision == "f32" else 8
     per_pf = sx + (1 + ss if has_mask else 0) + ss + ss + ss
     if precision == "mixed":
         per_pf += 4 + 4
-    return n * p * per_pf + 40 * E, per_pf
+    return n * p * per_pf + 24 * E, per_pf
 
 
 TRAFFIC_PROFILES = {
@@ -203,6 +218,9 @@ def cpu_baseline(wl, seconds):
         "kind": "oracle",
         "sample": f"{it} MM iterations (exact projection) at gamma=30 on the n={wl.n}, p={wl.p} "
                   f"workload, {dt:.1f} s; setup excluded",
+        "host": {**host_cpu(), "blas_threads": threads,
+                 "threads_note": "the exact projection's Cholesky solve runs on the BLAS threads; "
+                                 "the sparse products and elementwise steps on one thread"},
     }
 
 
@@ -248,9 +266,13 @@ def bench_batched(args):
     tune_s = time.perf_counter() - t0
     cfg = bt.config()
     t0 = time.perf_counter()
-    _, infos, lat = bt.run(labels=True)
+    labs, infos, lat = bt.run(labels=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # one small instance's results, for the comparison with the oracle
+    ob = ORACLE_BATCH_INSTANCE if ORACLE_BATCH_INSTANCE < N else 0
+    sample = {"instance": ob, "labels": labs[ob].cpu().numpy(), "infos": infos[ob],
+              "U": inst[ob][0].U(torch.float64).cpu().numpy()}
     solves = sum(len(g) for _, g in inst)
     print(f"[bench] batched: {N} instances, {solves} solves in {wall:.2f}s", file=sys.stderr, flush=True)
     bt.close()
@@ -279,6 +301,40 @@ def bench_batched(args):
         "accuracy": _accuracy([i for inf in infos for i in inf], args.batch_tol),
         "plain": {"sample": len(times), "solves_per_s": psolves / sum(times), "mean_path_s": mean_path,
                   "fifo_latency_ms_estimated": {"p50": 1e3 * _pct(fifo, 50), "p99": 1e3 * _pct(fifo, 99)}},
+        "oracle_sample": sample,
+    }
+
+
+ORACLE_BATCH_INSTANCE = 14  # n = 82, p = 83: the oracle runs its 16-gamma path in seconds
+
+
+def batched_oracle_parity(sample, args):
+    """A batched instance's results against the FP64 oracle on the oracle's
+    own kNN weights (same stopping rule and cap): gammas whose stopping test
+    passed on both sides, whether their labels agree, and the centres' error
+    after the path."""
+    import numpy as np
+
+    import gen
+    from oracle import mm, weights
+    b = sample["instance"]
+    wl = gen.batched_instance(b)
+    X = np.asarray(wl.X, dtype=np.float32).astype(np.float64)
+    E, w, _ = weights.knn_weights(X, None, wl.k, wl.phi)
+    t0 = time.perf_counter()
+    _, oinf, oU = mm.Problem(X, None, E, w).solve_path(
+        [float(g) for g in wl.gammas], mm.Opts(proj="jacobi:1", max_iter=args.batch_max_iter, tol=args.batch_tol))
+    cpu_s = time.perf_counter() - t0
+    conv = [k for k, oi in enumerate(oinf) if oi.converged and sample["infos"][k]["converged"]]
+    labels_equal = all(np.array_equal(sample["labels"][k], oinf[k].labels) for k in conv)
+    return {
+        "instance": b, "n": wl.n, "p": wl.p, "gammas": len(oinf),
+        "converged_both": len(conv),
+        "converged_oracle_only": sum(1 for k, oi in enumerate(oinf) if oi.converged and not sample["infos"][k]["converged"]),
+        "labels_equal_where_converged": bool(labels_equal),
+        "U_max_rel_diff_after_path": float(np.abs(sample["U"] - oU[-1]).max() / np.abs(oU[-1]).max()),
+        "bar": {"U_rel": 1e-5},
+        "oracle_s": round(cpu_s, 2),
     }
 
 
@@ -381,6 +437,159 @@ def bench_extras(X, M, edges, w, gammas, args):
     }
 
 
+def host_cpu():
+    """The host the CPU baseline runs on: logical CPUs, those this process may
+    use, and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 0
+    return {"nproc": os.cpu_count() or 0, "usable": usable, "model": model}
+
+
+def run_workload(cc, name, precision, steps, warmup, max_iter, sample_every, log):
+    """One workload's timed path: inputs on the device, kNN weights built
+    (timed separately), then `steps` timed steps of reset + the warm-started
+    gamma path with labels, each gamma capped at max_iter MM iterations.
+    Returns the result fields and the device inputs."""
+    import numpy as np
+    import torch
+
+    import gen
+    dev = torch.device("cuda:0")
+    wl = gen.make(name)
+    n, p = wl.n, wl.p
+    X = torch.tensor(np.nan_to_num(wl.X), dtype=torch.float32, device=dev)
+    M = None if wl.mask is None else torch.tensor(wl.mask.astype(np.uint8), device=dev)
+    if wl.standardize:
+        cc.standardize_columns(X, M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    edges, w, phi_used = cc.build_knn_weights(X, M, k=wl.k, phi=wl.phi)
+    torch.cuda.synchronize()
+    knn_s = time.perf_counter() - t0
+    E = int(edges.shape[0])
+    prob = cc.Problem(X, M, edges, w, precision=precision)
+    gammas = [float(g) for g in wl.gammas]
+    opts = dict(max_iter=max_iter, warm_start=1)
+
+    def step():
+        prob.reset_state()
+        infos, labels, _ = prob.solve_path(gammas, labels=True, **opts)
+        return infos, labels
+
+    for k in range(warmup):
+        step()
+        log(f"{name}: warmup step {k + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    prob.profile(sample_every)
+    iters = 0
+    converged = 0
+    clusters = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        infos, labels = step()
+        log(f"{name}: timed step {k + 1}/{steps} done")
+        iters += sum(i["iters"] for i in infos)
+        converged += sum(i["converged"] for i in infos)
+        clusters = [i["n_clusters"] for i in infos]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ks = prob.kernel_stats()
+    prob.profile(0)
+    prob.close()
+
+    has_mask = M is not None
+    alg_point, alg_iter, k1 = algorithmic_bytes(n, p, E, has_mask)
+    impl_point, impl_pf = implementation_bytes(n, p, E, precision, has_mask)
+    pt_ms = ks["point_sweep"]["avg_ms"]
+    iter_ms = dt * 1e3 / max(iters, 1)
+    achieved = alg_point / (pt_ms * 1e-3) / 1e9 if pt_ms > 0 else 0.0
+    it_achieved = alg_iter / (iter_ms * 1e-3) / 1e9 if iter_ms > 0 else 0.0
+    out = {
+        "value": iters * E * p / dt,
+        "ms_per_step": dt * 1e3 / steps,
+        "config": {
+            "workload": WORKLOAD_TEXT[name] + ("" if max_iter >= 20000 else f", at most {max_iter} MM iterations per gamma"),
+            "n": n, "p": p, "edges": E, "gammas": len(gammas), "precision": precision,
+            "mm_iterations_per_step": iters // max(steps, 1),
+            "gammas_converged_per_step": converged // max(steps, 1),
+            "clusters_along_path": clusters,
+            "knn_build_s": round(knn_s, 4),
+            "phi": phi_used,
+            "kernel_ms": {k: round(v["avg_ms"], 5) for k, v in ks.items()},
+            "iteration_ms_kernels": round(sum(v["avg_ms"] for v in ks.values()), 5),
+            "iteration_ms_wall": round(iter_ms, 5),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_point (point sweep: U update + Jacobi projection sweep)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": stored_traffic(name, precision),
+            "bytes_per_launch": alg_point,
+            "bytes_per_point_feature": k1,
+            "bytes_rule": f"{k1} B per point-feature (FP32 state: X, "
+                          + ("mask, " if has_mask else "") + "U read and write, A' read, A write) + 24 B per edge",
+            "precision_overhead_bytes": impl_point - alg_point,
+            "implementation_bytes_per_point_feature": impl_pf,
+            "iteration": {"bytes": alg_iter, "bytes_rule": f"{k1 + 8} B per point-feature + 60 B per edge",
+                          "achieved": it_achieved, "frac": it_achieved / HBM_PEAK_GBS},
+        },
+    }
+    return out, (X, M, edges, w, gammas, wl)
+
+
+def oracle_parity(cc, X, M, edges, w, wl, gamma=30.0, iters=20):
+    """The error against the FP64 oracle of the configuration the headline
+    times: the oracle's own kNN weights (edge set compared with the GPU's),
+    then `iters` MM iterations at `gamma` from the initial state on both
+    sides, the oracle with one Jacobi sweep per iteration as the GPU; max
+    relative differences of U and A, the largest shrink-factor difference,
+    and whether the fused edges agree."""
+    import numpy as np
+    import torch
+
+    from oracle import mm, weights
+    Xh = np.asarray(wl.X, dtype=np.float32).astype(np.float64)
+    E, wo, _ = weights.knn_weights(Xh, wl.mask, wl.k, wl.phi)
+    Eg = edges.cpu().numpy()
+    same_edges = bool(Eg.shape == E.shape and np.array_equal(Eg, E))
+    w_rel = float(np.abs(w.cpu().numpy() - wo).max() / np.abs(wo).max()) if same_edges else None
+    t0 = time.perf_counter()
+    st, info = mm.Problem(Xh, wl.mask, E, wo).solve(gamma, mm.Opts(tol=0, max_iter=iters, proj="jacobi:1"))
+    cpu_s = time.perf_counter() - t0
+    with cc.Problem(X, M, edges, w, precision="mixed") as g:
+        g.solve(gamma, tol=0.0, max_iter=iters)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+    return {
+        "workload": "expression n=2000 p=500 (the headline's inputs)",
+        "oracle": "FP64, one Jacobi sweep per MM iteration, from the initial state",
+        "gamma": gamma, "mm_iterations": iters,
+        "knn_edges_equal": same_edges, "weights_max_rel_diff": w_rel,
+        "U_max_rel_diff": rel(U, st.U), "A_max_rel_diff": rel(A, st.A),
+        "s_max_abs_diff": float(np.abs(s - st.s).max()),
+        "fused_edges_equal": bool(np.array_equal(s == 0, st.s == 0)),
+        "bar": {"U_A_rel": 2e-6, "s_abs": 1e-6},
+        "oracle_s": round(cpu_s, 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +602,10 @@ def main():
     ap.add_argument("--sample-every", type=int, default=8, help="kernel timing sample period")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-genotype", action="store_true")
+    ap.add_argument("--genotype-steps", type=int, default=3)
+    ap.add_argument("--genotype-max-iter", type=int, default=50)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--batch-max-iter", type=int, default=5000)
@@ -420,11 +633,12 @@ def main():
               "feature sharding across GPUs is described in the design notes and not implemented.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    import gen
     import paper_1409_2065_amd as cc
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     cc.load()
     dev = torch.device("cuda:0")
@@ -435,99 +649,49 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        print(f"[bench] copied {args.calibrate_copy_mib} MiB for counter calibration", file=sys.stderr, flush=True)
-    wl = gen.make(args.workload)
+        log(f"copied {args.calibrate_copy_mib} MiB for counter calibration")
+    head, (X, M, edges, w, gammas, wl) = run_workload(
+        cc, args.workload, args.precision, args.steps, args.warmup, args.max_iter, args.sample_every, log)
     n, p = wl.n, wl.p
-    X = torch.tensor(np.nan_to_num(wl.X), dtype=torch.float32, device=dev)
-    M = None if wl.mask is None else torch.tensor(wl.mask.astype(np.uint8), device=dev)
-    if wl.standardize:
-        cc.standardize_columns(X, M)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    edges, w, phi_used = cc.build_knn_weights(X, M, k=wl.k, phi=wl.phi)
-    torch.cuda.synchronize()
-    knn_s = time.perf_counter() - t0
-    E = int(edges.shape[0])
-    prob = cc.Problem(X, M, edges, w, precision=args.precision)
-    gammas = [float(g) for g in wl.gammas]
-    opts = dict(max_iter=args.max_iter, warm_start=1)
-
-    def step():
-        prob.reset_state()
-        infos, labels, _ = prob.solve_path(gammas, labels=True, **opts)
-        return infos, labels
-
-    for k in range(args.warmup):
-        step()
-        print(f"[bench] warmup step {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    prob.profile(args.sample_every)
-    iters = 0
-    converged = 0
-    clusters = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        infos, labels = step()
-        print(f"[bench] timed step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
-        iters += sum(i["iters"] for i in infos)
-        converged += sum(i["converged"] for i in infos)
-        clusters = [i["n_clusters"] for i in infos]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ks = prob.kernel_stats()
-    prob.profile(0)
-
-    value = iters * E * p / dt
-    bytes_launch, per_pf = point_sweep_bytes(n, p, E, args.precision, M is not None)
-    pt_ms = ks["point_sweep"]["avg_ms"]
-    achieved = bytes_launch / (pt_ms * 1e-3) / 1e9 if pt_ms > 0 else 0.0
-    iter_ms = sum(v["avg_ms"] for v in ks.values())
     result = {
         "metric": METRIC if args.workload == "expression" else f"pair-feature updates/s (n={n},p={p})",
-        "value": value,
+        "value": head["value"],
         "unit": "pair-feature updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"mixed": "f64 point state, f32 pair gathers", "f32": "f32", "f64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {
-            "workload": WORKLOAD_TEXT[args.workload],
-            "n": n, "p": p, "edges": E, "gammas": len(gammas), "precision": args.precision,
-            "mm_iterations_per_step": iters // max(args.steps, 1),
-            "gammas_converged_per_step": converged // max(args.steps, 1),
-            "clusters_along_path": clusters,
-            "knn_build_s": round(knn_s, 4),
-            "phi": phi_used,
-            "kernel_ms": {k: round(v["avg_ms"], 5) for k, v in ks.items()},
-            "iteration_ms_kernels": round(iter_ms, 5),
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_point (point sweep: U update + Jacobi projection sweep)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": stored_traffic(args.workload, args.precision),
-            "bytes_per_launch": bytes_launch,
-            "bytes_per_point_feature": per_pf,
-        },
+        "config": head["config"],
+        "roofline": head["roofline"],
     }
-    prob.close()
     if not args.no_extras and args.workload == "expression":
         result["extras"] = bench_extras(X, M, edges, w, gammas, args)
-        print("[bench] extras done", file=sys.stderr, flush=True)
+        log("extras done")
+    if not args.no_genotype and args.workload == "expression":
+        geno, _ = run_workload(cc, "genotype", args.precision, args.genotype_steps, 1, args.genotype_max_iter,
+                               args.sample_every, log)
+        result["genotype"] = {"metric": "pair-feature updates/s (n=1000,p=20000)", "unit": "pair-feature updates/s",
+                              "steps": args.genotype_steps, **geno}
+    batched = None
     if not args.no_batched:
-        result["batched"] = bench_batched(args)
+        result["batched"] = batched = bench_batched(args)
     if not args.no_served:
         result["served"] = bench_served(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        log("cpu baseline done")
+        if not args.no_parity and args.workload == "expression":
+            result["parity"] = {"expression": oracle_parity(cc, X, M, edges, w, wl)}
+            if batched is not None and "oracle_sample" in batched:
+                result["parity"]["batched"] = batched_oracle_parity(batched.pop("oracle_sample"), args)
+            log("parity done")
+    if batched is not None:
+        batched.pop("oracle_sample", None)
     print(json.dumps(result), flush=True)
 
 

@@ -17,15 +17,35 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in out.stderr
 
 
-# without a mask the point sweep reads U only in a solve's first iteration,
-# so the U read (8 B, or 4 B in f32) is not algorithmic traffic
+# the graded bytes follow the method at FP32 state (X, mask with missing
+# data, U read and write, A' read, A write): 21 B per point-feature with a
+# mask, 20 without, and 24 B per edge for the point sweep's neighbour slots
+# and q factors; the whole iteration adds the edge stage's 8 B per
+# point-feature and comes to 60 B per edge
+@pytest.mark.parametrize("mask,k1", [(True, 21), (False, 20)])
+def test_algorithmic_bytes(mask, k1):
+    point, it, per_pf = bench.algorithmic_bytes(2000, 500, 22965, mask)
+    assert per_pf == k1
+    assert point == 2000 * 500 * k1 + 24 * 22965
+    assert it == 2000 * 500 * (k1 + 8) + 60 * 22965
+
+
+# what this implementation moves: without a mask the point sweep reads U only
+# in a solve's first iteration; the mixed precision keeps FP64 U and A and
+# an FP32 gather copy of A
 @pytest.mark.parametrize("prec,mask,expect", [("mixed", True, 45), ("f32", True, 21),
                                               ("f64", True, 41), ("mixed", False, 36),
                                               ("f32", False, 16)])
-def test_point_sweep_bytes(prec, mask, expect):
-    b, per_pf = bench.point_sweep_bytes(2000, 500, 22965, prec, mask)
+def test_implementation_bytes(prec, mask, expect):
+    b, per_pf = bench.implementation_bytes(2000, 500, 22965, prec, mask)
     assert per_pf == expect
-    assert b == 2000 * 500 * expect + 40 * 22965
+    assert b == 2000 * 500 * expect + 24 * 22965
+
+
+def test_host_cpu_description():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and 1 <= h["usable"] <= h["nproc"]
+    assert isinstance(h["model"], str)
 
 
 def _fake_counters(path, counter, copy_kib, kp_kib):
