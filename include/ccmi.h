@@ -303,6 +303,23 @@ cc_status cc_standardize_columns(int64_t n, int64_t p, int32_t x_dtype,
                                  void *X, int64_t ldx, const uint8_t *mask,
                                  int64_t ldm, void *stream);
 
+/* cc_standardize_columns_noalloc: for callers that cannot allocate device
+ * memory (code between the allocation points of a serving loop, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as
+ * cc_standardize_columns, but the column statistics live in a fixed device
+ * array of the library instead of memory allocated per call: it calls no
+ * hipMalloc or hipFree.  Each GPU the library runs on holds 1 MiB of it
+ * until the process ends.  Takes p <= 65536 (CC_ERR_INVALID_ARG beyond,
+ * nothing written).  Every call on a GPU uses that GPU's one array, so calls
+ * that overlap on one GPU (from several host threads or on unordered
+ * streams) race; calls ordered on one stream, or separated by a
+ * synchronisation, do not.  Like cc_standardize_columns it synchronises the
+ * stream (it reads back the count of non-finite observed entries). */
+cc_status cc_standardize_columns_noalloc(int64_t n, int64_t p, int32_t x_dtype,
+                                         void *X, int64_t ldx,
+                                         const uint8_t *mask, int64_t ldm,
+                                         void *stream);
+
 /* cc_components: connected components of the subgraph of edges with
  * keep[e] != 0 (device uint8, may be NULL = all), labels (device int32, n)
  * = smallest index in each component; n_components host output. */

@@ -80,6 +80,7 @@ SIGNATURES = {
     "cc_get_state": (i32, [vp, vp, vp, i64, vp]),
     "cc_build_knn_weights": (i32, [i64, i64, i32, vp, i64, vp, i64, i32, f64, i32, vp, vp, vp, i64, P_i64, P_f64, vp]),
     "cc_standardize_columns": (i32, [i64, i64, i32, vp, i64, vp, i64, vp]),
+    "cc_standardize_columns_noalloc": (i32, [i64, i64, i32, vp, i64, vp, i64, vp]),
     "cc_components": (i32, [i64, i64, vp, vp, vp, vp, P_i32, vp]),
     "cc_pca": (i32, [i64, i64, i32, vp, i64, vp, i64, i32, i32, vp, P_f64, vp, vp]),
     "cc_solve_path_pc": (i32, [vp, i32, P_f64, C.POINTER(SolveOpts), vp, i32, vp, vp, vp,

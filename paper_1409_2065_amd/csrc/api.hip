@@ -520,6 +520,13 @@ cc_status cc_standardize_columns(int64_t n, int64_t p, int32_t x_dtype, void *X,
   CC_GUARD_END
 }
 
+cc_status cc_standardize_columns_noalloc(int64_t n, int64_t p, int32_t x_dtype, void *X, int64_t ldx,
+                                         const uint8_t *mask, int64_t ldm, void *stream) {
+  CC_GUARD_BEGIN
+  return standardize_columns_noalloc(n, p, x_dtype, X, ldx, mask, ldm, (hipStream_t)stream);
+  CC_GUARD_END
+}
+
 cc_status cc_pca(int64_t n, int64_t p, int32_t x_dtype, const void *X, int64_t ldx,
                  const uint8_t *mask, int64_t ldm, int32_t r, int32_t iters, double *V,
                  double *sval, double *center, void *stream) {

@@ -292,6 +292,9 @@ cc_status build_knn_weights(int64_t n, int64_t p, int32_t x_dtype,
 cc_status standardize_columns(int64_t n, int64_t p, int32_t x_dtype, void *X,
                               int64_t ldx, const uint8_t *mask, int64_t ldm,
                               hipStream_t stream);
+cc_status standardize_columns_noalloc(int64_t n, int64_t p, int32_t x_dtype, void *X,
+                                      int64_t ldx, const uint8_t *mask, int64_t ldm,
+                                      hipStream_t stream);
 cc_status min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *X,
                           int64_t ldx, const uint8_t *mask, int64_t ldm,
                           int32_t k_max, int32_t *k_min, int32_t *n_components,

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "ccmi_internal.h"
@@ -811,6 +812,90 @@ cc_status standardize_columns(int64_t n, int64_t p, int32_t x_dtype, void *X, in
   else
     hipLaunchKernelGGL((k_standardize<double>), dim3(eb), dim3(256), 0, st, (int)n, (int)p,
                        (double *)X, ldx, mask, ldm, mean.as<double>(), sd.as<double>());
+  CC_HIP(hipGetLastError());
+  CC_HIP(hipStreamSynchronize(st));
+  return CC_OK;
+}
+
+// ------------------------------------------- standardisation without allocation
+// cc_standardize_columns_noalloc keeps the column statistics in this fixed
+// device array instead of memory allocated per call: the means, then the
+// standard deviations (kStdMaxCols doubles each), then the count of
+// non-finite observed entries.  Each GPU holds its own copy; host code uses
+// the device address hipGetSymbolAddress gives on that GPU, never the
+// array's name.
+constexpr int64_t kStdMaxCols = 65536;
+static __device__ __align__(256) double scratch[2 * kStdMaxCols + 32];
+
+constexpr int kMaxScratchDevices = 256;
+static std::mutex g_scratch_mutex;
+static void *g_scratch_addr[kMaxScratchDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static cc_status scratch_address(void **out) {
+  int dev = 0;
+  CC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    set_error("device index beyond the library's scratch table");
+    return CC_ERR_STATE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) {
+      set_error("hipGetSymbolAddress(scratch) gave no address");
+      return CC_ERR_HIP;
+    }
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return CC_OK;
+}
+
+__global__ void k_zero_count(int *count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0;
+}
+
+cc_status standardize_columns_noalloc(int64_t n, int64_t p, int32_t x_dtype, void *X, int64_t ldx,
+                                      const uint8_t *mask, int64_t ldm, hipStream_t st) {
+  if (n < 1 || p < 1) { set_error("need n, p >= 1"); return CC_ERR_INVALID_ARG; }
+  if (!X) { set_error("X is NULL"); return CC_ERR_INVALID_ARG; }
+  if (ldx < p || (mask && ldm < p)) { set_error("leading dimension < p"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype != CC_DTYPE_F32 && x_dtype != CC_DTYPE_F64) { set_error("bad x_dtype"); return CC_ERR_INVALID_ARG; }
+  if ((int64_t)n * p > ((int64_t)1 << 31) - 1) { set_error("n * p too large"); return CC_ERR_INVALID_ARG; }
+  if (p > kStdMaxCols) {
+    set_error("cc_standardize_columns_noalloc takes p <= " + std::to_string(kStdMaxCols) +
+              " (the size of its fixed device scratch)");
+    return CC_ERR_INVALID_ARG;
+  }
+  void *base = nullptr;
+  KN_TRY(scratch_address(&base));
+  double *mean = reinterpret_cast<double *>(base);
+  double *sd = mean + kStdMaxCols;
+  int *bad = reinterpret_cast<int *>(sd + kStdMaxCols);
+  // the array keeps the last call's contents: the count starts at zero
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, st, bad);
+  const int cb = (int)cdiv64(p, 256), eb = (int)cdiv64(n * p, 256);
+  if (x_dtype == CC_DTYPE_F32)
+    hipLaunchKernelGGL((k_col_moments<float>), dim3(cb), dim3(256), 0, st, (int)n, (int)p,
+                       (const float *)X, ldx, mask, ldm, mean, sd, bad);
+  else
+    hipLaunchKernelGGL((k_col_moments<double>), dim3(cb), dim3(256), 0, st, (int)n, (int)p,
+                       (const double *)X, ldx, mask, ldm, mean, sd, bad);
+  CC_HIP(hipGetLastError());
+  int hbad = 0;
+  CC_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (hbad) { set_error("observed X has non-finite entries"); return CC_ERR_INVALID_ARG; }
+  if (x_dtype == CC_DTYPE_F32)
+    hipLaunchKernelGGL((k_standardize<float>), dim3(eb), dim3(256), 0, st, (int)n, (int)p,
+                       (float *)X, ldx, mask, ldm, mean, sd);
+  else
+    hipLaunchKernelGGL((k_standardize<double>), dim3(eb), dim3(256), 0, st, (int)n, (int)p,
+                       (double *)X, ldx, mask, ldm, mean, sd);
   CC_HIP(hipGetLastError());
   CC_HIP(hipStreamSynchronize(st));
   return CC_OK;
