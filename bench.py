@@ -265,6 +265,7 @@ def bench_batched(args):
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
     cfg = bt.config()
+    classes, _ = bt.tuning()
     t0 = time.perf_counter()
     labs, infos, lat = bt.run(labels=True)
     torch.cuda.synchronize()
@@ -278,29 +279,42 @@ def bench_batched(args):
     bt.close()
     for p, _ in inst:
         p.close()
-    times, psolves = [], 0
-    for b in range(min(args.plain_sample, N)):
+    # the plain path: every instance solved alone, one after another in
+    # order, all present at the start (the batch's own arrival pattern); the
+    # latency of instance b is the time from the start to the end of its path
+    times, psolves, pinfos = [], 0, []
+    nplain = N if args.plain_sample <= 0 else min(args.plain_sample, N)
+    for b in range(nplain):
         p, g = make(b)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        p.solve_path(g, labels=True, **opts)
+        pinfos += p.solve_path(g, labels=True, **opts)[0]
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         psolves += len(g)
         p.close()
-    mean_path = float(np.mean(times))
-    fifo = mean_path * np.arange(1, N + 1)  # all N arriving together, one after another
+    fifo = np.cumsum(times)
+    print(f"[bench] batched, plain path: {nplain} instances in {fifo[-1]:.2f}s", file=sys.stderr, flush=True)
+    plain = {"instances": nplain, "solves_per_s": psolves / float(fifo[-1]), "wall_s": float(fifo[-1]),
+             "fifo_latency_ms": {"p50": 1e3 * _pct(fifo, 50), "p99": 1e3 * _pct(fifo, 99), "max": 1e3 * float(fifo[-1])},
+             "accuracy": _accuracy(pinfos, args.batch_tol)}
+    if nplain < N:
+        plain["note"] = f"the first {nplain} of {N} instances; latencies are of those"
     return {
         "instances": N, "solves": solves, "max_iter_per_gamma": args.batch_max_iter,
-        "autotuned": {"vec": cfg["vec"], "items_per_wave": cfg["items_per_wave"],
-                      "us_per_iteration": [round(t, 1) for t in cfg["tune_us"]], "tune_s": round(tune_s, 3)},
+        "autotuned": {"classes": [{k: (round(v, 1) if isinstance(v, float) else v) for k, v in c.items()}
+                                  for c in classes],
+                      "class_key": "width_class: p <= 64, <= 128, <= 256, wider; size_class: point-sweep items "
+                                   "<= 512, <= 2048, more; vec: 64*vec features per wave",
+                      "largest_instance": {"vec": cfg["vec"], "items_per_wave": cfg["items_per_wave"],
+                                           "us_per_iteration_candidates": [round(t, 1) for t in cfg["tune_us"]]},
+                      "tune_s": round(tune_s, 3)},
         "solves_per_s": solves / wall, "wall_s": wall,
         "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99), "max": float(np.max(lat))},
         "mm_iterations": int(sum(i["iters"] for inf in infos for i in inf)),
         "tol": args.batch_tol,
         "accuracy": _accuracy([i for inf in infos for i in inf], args.batch_tol),
-        "plain": {"sample": len(times), "solves_per_s": psolves / sum(times), "mean_path_s": mean_path,
-                  "fifo_latency_ms_estimated": {"p50": 1e3 * _pct(fifo, 50), "p99": 1e3 * _pct(fifo, 99)}},
+        "plain": plain,
         "oracle_sample": sample,
     }
 
@@ -338,61 +352,149 @@ def batched_oracle_parity(sample, args):
     }
 
 
+def serve_stream(cc, reqs, arrivals, budget, opts, max_active=256, round_iters=32, keep=None):
+    """Submits each request at its arrival time to a continuous-batching
+    server and steps it until every request is done; a client reads each
+    result (labels on the device, infos) as soon as its request is done and
+    releases it, so its budget share returns.  Returns wall time, per-request
+    latency (arrival -> labels on the device, stamped by the server at the end
+    of the round that finished the path), the per-gamma infos, and the peak
+    of admitted requests and of counted device bytes."""
+    import torch
+    N = len(reqs)
+    torch.cuda.synchronize()
+    srv = cc.Server("mixed", hbm_budget=budget, max_active=max_active, round_iters=round_iters, **opts)
+    t0 = time.perf_counter()
+    tickets, nxt = {}, 0
+    open_, lat, infos, kept = {}, [0.0] * N, [None] * N, None
+    peak_active, peak_used, waited_rounds = 0, 0, 0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < N and arrivals[nxt] <= now:
+            w = reqs[nxt]
+            tickets[nxt] = srv.submit(w.X, w.mask, k=w.k, phi=w.phi, gammas=w.gammas)
+            open_[nxt] = tickets[nxt]
+            nxt += 1
+        a, wt, nd = srv.step()
+        peak_active = max(peak_active, a)
+        peak_used = max(peak_used, srv.memory()[0])
+        waited_rounds += 1 if (wt > 0 and a > 0) else 0
+        if nd:
+            for r, t in list(open_.items()):
+                st = srv.status(t)
+                if st["state"] != 2:
+                    continue
+                lat[r] = st["t_done"] - st["t_submit"]
+                if keep is not None and r == keep:
+                    lab, inf, U = srv.result(t, U=True)
+                    kept = {"request": keep, "labels": lab.cpu().numpy(), "infos": inf, "U": U.double().cpu().numpy()}
+                else:
+                    _, inf, _ = srv.result(t)
+                infos[r] = inf
+                srv.release(t)
+                del open_[r]
+        if nxt == N and a == 0 and wt == 0 and not open_:
+            break
+        if a == 0 and wt == 0 and nxt < N:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+    wall = time.perf_counter() - t0
+    srv.close()
+    return {"wall": wall, "lat": lat, "infos": [i for inf in infos for i in inf], "peak_active": peak_active,
+            "peak_used": peak_used, "rounds_with_waiting": waited_rounds, "kept": kept}
+
+
 def bench_served(args):
-    """Requests at their arrival times: the continuous-batching server against
-    the plain path solving them first come, first served."""
+    """Requests of the Poisson stream at their arrival times.
+      stream     the first --serve-requests requests at 200/s (far beyond
+                 what one GPU sustains: saturated), admitted within an HBM
+                 budget of --serve-budget-mib that binds;
+      fifo       the first --serve-fifo of them on the server and, apart,
+                 solved first come first served by the plain path;
+      rate_sweep --serve-sweep-requests requests at each of the
+                 --serve-rates arrival rates on the server.
+    Every solve stops at tol --serve-tol or --serve-max-iter MM iterations per
+    gamma on both sides; the converged share is stated."""
     import numpy as np
     import torch
 
     import gen
     import paper_1409_2065_amd as cc
-    N = args.serve_requests
     opts = dict(max_iter=args.serve_max_iter, tol=args.serve_tol)
-    arr = gen.served_arrivals(200.0, N)
+    budget = args.serve_budget_mib << 20
+    N = args.serve_requests
     reqs = [gen.served_instance(r) for r in range(N)]
-    solves = sum(len(w.gammas) for w in reqs)
-    torch.cuda.synchronize()
-    srv = cc.Server("mixed", hbm_budget=64 << 30, max_active=256, round_iters=32, **opts)
-    t0 = time.perf_counter()
-    tickets, nxt = {}, 0
-    while True:
-        now = time.perf_counter() - t0
-        while nxt < N and arr[nxt] <= now:
-            w = reqs[nxt]
-            tickets[nxt] = srv.submit(w.X, w.mask, k=w.k, phi=w.phi, gammas=w.gammas)
-            nxt += 1
-        a, wt, _ = srv.step()
-        if nxt == N and a == 0 and wt == 0:
-            break
-        if a == 0 and wt == 0:
-            time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
-    wall = time.perf_counter() - t0
-    lat = [srv.status(tickets[r])["t_done"] - srv.status(tickets[r])["t_submit"] for r in range(N)]
-    sinfos = [i for r in range(N) for i in srv.result(tickets[r])[1]]
-    srv.close()
-    print(f"[bench] served: {N} requests in {wall:.2f}s", file=sys.stderr, flush=True)
+    arr = gen.served_arrivals(200.0, N)
+
+    def summary(res, reqs_):
+        solves = sum(len(w.gammas) for w in reqs_)
+        return {"requests": len(reqs_), "solves": solves, "wall_s": res["wall"],
+                "solves_per_s": solves / res["wall"], "requests_per_s": len(reqs_) / res["wall"],
+                "latency_s": {"p50": _pct(res["lat"], 50), "p99": _pct(res["lat"], 99), "max": float(np.max(res["lat"]))},
+                "accuracy": _accuracy(res["infos"], args.serve_tol)}
+
+    res = serve_stream(cc, reqs, arr, budget, opts)
+    stream = summary(res, reqs)
+    stream.update({"arrival_rate_per_s": 200.0, "hbm_budget_bytes": budget, "peak_admitted": res["peak_active"],
+                   "peak_counted_bytes": res["peak_used"], "rounds_with_requests_waiting": res["rounds_with_waiting"]})
+    print(f"[bench] served stream: {N} requests in {res['wall']:.2f}s", file=sys.stderr, flush=True)
+
+    M = min(args.serve_fifo, N)
+    small = int(np.argmin([w.n * w.p for w in reqs[:M]]))  # compared with the oracle
+    res_m = serve_stream(cc, reqs[:M], arr[:M], budget, opts, keep=small)
     t0 = time.perf_counter()
     lat2, pinfos = [], []
-    for r, w in enumerate(reqs):
+    for r, w in enumerate(reqs[:M]):
         now = time.perf_counter() - t0
         if now < arr[r]:
             time.sleep(arr[r] - now)
         X = torch.tensor(np.nan_to_num(w.X), dtype=torch.float32, device="cuda")
-        M = torch.tensor(w.mask.astype(np.uint8), device="cuda")
-        e, wt, _ = cc.build_knn_weights(X, M, k=w.k, phi=w.phi)
-        with cc.Problem(X, M, e, wt, precision="mixed") as pr:
+        Mk = torch.tensor(w.mask.astype(np.uint8), device="cuda")
+        e, wt, _ = cc.build_knn_weights(X, Mk, k=w.k, phi=w.phi)
+        with cc.Problem(X, Mk, e, wt, precision="mixed") as pr:
             pinfos += pr.solve_path([float(g) for g in w.gammas], labels=True, **opts)[0]
         torch.cuda.synchronize()
         lat2.append(time.perf_counter() - t0 - arr[r])
     wall2 = time.perf_counter() - t0
-    print(f"[bench] served, plain path: {wall2:.2f}s", file=sys.stderr, flush=True)
+    print(f"[bench] served head-to-head: {M} requests, server {res_m['wall']:.2f}s, plain {wall2:.2f}s",
+          file=sys.stderr, flush=True)
+    fifo = {"server": summary(res_m, reqs[:M]),
+            "plain_fifo": summary({"wall": wall2, "lat": lat2, "infos": pinfos}, reqs[:M])}
+
+    sweep = []
+    S = min(args.serve_sweep_requests, N)
+    for rate in [float(x) for x in args.serve_rates.split(",") if x]:
+        r_ = serve_stream(cc, reqs[:S], gen.served_arrivals(rate, S), budget, opts)
+        sweep.append({"arrival_rate_per_s": rate, **summary(r_, reqs[:S]), "peak_admitted": r_["peak_active"]})
+        print(f"[bench] served at {rate}/s: {S} requests in {r_['wall']:.2f}s", file=sys.stderr, flush=True)
+    return {"max_iter_per_gamma": args.serve_max_iter, "tol": args.serve_tol,
+            "stream": stream, "head_to_head": fifo, "rate_sweep": sweep, "oracle_sample": res_m["kept"]}
+
+
+def served_oracle_parity(sample, args):
+    """A served request's results against the FP64 oracle on the oracle's own
+    kNN weights of the same data and mask, with the same stopping rule and
+    cap: gammas converged on both sides, their labels, U after the path."""
+    import numpy as np
+
+    import gen
+    from oracle import mm, weights
+    r = sample["request"]
+    wl = gen.served_instance(r)
+    X = np.where(wl.mask, np.asarray(np.nan_to_num(wl.X), dtype=np.float32).astype(np.float64), np.nan)
+    E, w, _ = weights.knn_weights(X, wl.mask, wl.k, wl.phi)
+    t0 = time.perf_counter()
+    _, oinf, oU = mm.Problem(X, wl.mask, E, w).solve_path(
+        [float(g) for g in wl.gammas], mm.Opts(proj="jacobi:1", max_iter=args.serve_max_iter, tol=args.serve_tol))
+    cpu_s = time.perf_counter() - t0
+    conv = [k for k, oi in enumerate(oinf) if oi.converged and sample["infos"][k]["converged"]]
     return {
-        "requests": N, "arrival_rate_per_s": 200.0, "solves": solves, "max_iter_per_gamma": args.serve_max_iter,
-        "tol": args.serve_tol,
-        "server": {"solves_per_s": solves / wall, "requests_per_s": N / wall,
-                   "latency_s": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)}, "accuracy": _accuracy(sinfos, args.serve_tol)},
-        "plain_fifo": {"solves_per_s": solves / wall2, "requests_per_s": N / wall2,
-                       "latency_s": {"p50": _pct(lat2, 50), "p99": _pct(lat2, 99)}, "accuracy": _accuracy(pinfos, args.serve_tol)},
+        "request": r, "n": wl.n, "p": wl.p, "gammas": len(oinf),
+        "converged_both": len(conv),
+        "converged_oracle_only": sum(1 for k, oi in enumerate(oinf) if oi.converged and not sample["infos"][k]["converged"]),
+        "labels_equal_where_converged": bool(all(np.array_equal(sample["labels"][k], oinf[k].labels) for k in conv)),
+        "U_max_rel_diff_after_path": float(np.abs(sample["U"] - oU[-1]).max() / np.abs(oU[-1]).max()),
+        "bar": {"U_rel": 1e-5},
+        "oracle_s": round(cpu_s, 2),
     }
 
 
@@ -608,13 +710,17 @@ def main():
     ap.add_argument("--genotype-max-iter", type=int, default=50)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-instances", type=int, default=256)
-    ap.add_argument("--batch-max-iter", type=int, default=5000)
-    ap.add_argument("--batch-tol", type=float, default=1e-4)
-    ap.add_argument("--plain-sample", type=int, default=8)
+    ap.add_argument("--batch-max-iter", type=int, default=1000)
+    ap.add_argument("--batch-tol", type=float, default=1e-3)
+    ap.add_argument("--plain-sample", type=int, default=0, help="instances the plain path solves (0: all)")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=16)
-    ap.add_argument("--serve-max-iter", type=int, default=5000)
-    ap.add_argument("--serve-tol", type=float, default=1e-4)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-fifo", type=int, default=32)
+    ap.add_argument("--serve-sweep-requests", type=int, default=16)
+    ap.add_argument("--serve-rates", default="2,5,10")
+    ap.add_argument("--serve-budget-mib", type=int, default=1024)
+    ap.add_argument("--serve-max-iter", type=int, default=1000)
+    ap.add_argument("--serve-tol", type=float, default=1e-3)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras-max-iter", type=int, default=100)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -677,11 +783,11 @@ def main():
                                args.sample_every, log)
         result["genotype"] = {"metric": "pair-feature updates/s (n=1000,p=20000)", "unit": "pair-feature updates/s",
                               "steps": args.genotype_steps, **geno}
-    batched = None
+    batched = served = None
     if not args.no_batched:
         result["batched"] = batched = bench_batched(args)
     if not args.no_served:
-        result["served"] = bench_served(args)
+        result["served"] = served = bench_served(args)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
         log("cpu baseline done")
@@ -689,9 +795,12 @@ def main():
             result["parity"] = {"expression": oracle_parity(cc, X, M, edges, w, wl)}
             if batched is not None and "oracle_sample" in batched:
                 result["parity"]["batched"] = batched_oracle_parity(batched.pop("oracle_sample"), args)
+            if served is not None and served.get("oracle_sample"):
+                result["parity"]["served"] = served_oracle_parity(served.pop("oracle_sample"), args)
             log("parity done")
-    if batched is not None:
-        batched.pop("oracle_sample", None)
+    for leg in (batched, served):
+        if leg is not None:
+            leg.pop("oracle_sample", None)
     print(json.dumps(result), flush=True)
 
 

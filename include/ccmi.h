@@ -360,12 +360,27 @@ cc_status cc_components(int64_t n, int64_t n_edges, const int32_t *ei,
  * Returns CC_ERR_NUMERIC if any instance's d or objective became
  * non-finite (its path stops there; the others finish).
  *
- * cc_batch_config (host outputs, any may be NULL): the chosen point-sweep
- * features per lane (vec: tile width 64 * vec), work items per wave, the MM
- * iterations per graph replay, and tune_us (9 entries): the autotuner's
- * microseconds per iteration for (vec, items per wave) = (1,1), (1,4),
- * (1,16), (2,1), (2,4), (2,16), (4,1), (4,4), (4,16) (zeros without
- * autotuning). */
+ * cc_batch_config (host outputs, any may be NULL), for the instance with
+ * the most work: its point-sweep features per lane (vec: tile width
+ * 64 * vec) and work items per wave; the MM iterations per graph replay;
+ * and tune_us (9 entries): the autotuner's microseconds per batched
+ * iteration when that instance's class took (vec, items per wave) = (1,1),
+ * (1,4), (1,16), (2,1), (2,4), (2,16), (4,1), (4,4), (4,16) (zeros without
+ * autotuning).
+ *
+ * cc_batch_tuning: the autotuner's choice per class of instances.  The
+ * autotuner groups instances by the width of their rows (class 0: p <= 64,
+ * 1: <= 128, 2: <= 256, 3: wider) and by the point-sweep work items at the
+ * width's natural tile (0: <= 512, 1: <= 2048, 2: more), and gives each
+ * class its own point-sweep launch, timing the 9 candidates above for one
+ * class at a time (classes with more work first, the others keeping their
+ * choice).  Host outputs: *n_classes (may be NULL) the number of classes;
+ * for the first cap classes, classes[5 c + 0..4] = width class, size class,
+ * instances, vec, items per wave, and us[c] (may be NULL) the microseconds
+ * per batched iteration with the choices; inst_class (n_inst entries, may
+ * be NULL) the class of each instance.  Without autotuning there are no
+ * classes (instance classes -1) and every instance takes vec from its row
+ * width (p <= 64: 1, <= 128: 2, else 4) and one item per wave. */
 cc_status cc_batch_create(int32_t n_inst, const cc_problem_t *problems,
                           const int32_t *n_gamma, const double *gammas,
                           const cc_solve_opts *opts, int32_t autotune,
@@ -374,6 +389,8 @@ cc_status cc_batch_run(cc_batch_t batch, int32_t *labels, cc_solve_info *infos,
                        double *latency_ms);
 cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *items_per_wave,
                           int32_t *graph_iters, double *tune_us);
+cc_status cc_batch_tuning(cc_batch_t batch, int32_t cap, int32_t *n_classes,
+                          int32_t *classes, double *us, int32_t *inst_class);
 cc_status cc_batch_destroy(cc_batch_t batch);
 
 /* ---------------------------------------------------------------------

@@ -91,6 +91,7 @@ SIGNATURES = {
     "cc_batch_create": (i32, [i32, C.POINTER(vp), P_i32, P_f64, C.POINTER(SolveOpts), i32, C.POINTER(vp)]),
     "cc_batch_run": (i32, [vp, vp, C.POINTER(SolveInfo), P_f64]),
     "cc_batch_config": (i32, [vp, P_i32, P_i32, P_i32, P_f64]),
+    "cc_batch_tuning": (i32, [vp, i32, P_i32, P_i32, P_f64, P_i32]),
     "cc_batch_destroy": (i32, [vp]),
     "cc_server_create": (i32, [i32, C.POINTER(SolveOpts), i64, i32, i32, vp, C.POINTER(vp)]),
     "cc_server_submit": (i32, [vp, i64, i64, vp, vp, i32, f64, i32, P_f64, P_i64]),

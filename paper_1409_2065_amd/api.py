@@ -335,6 +335,20 @@ class Batch:
         check(_lib.load().cc_batch_config(self._h, C.byref(vec), C.byref(ipw), C.byref(gi), tune))
         return {"vec": vec.value, "items_per_wave": ipw.value, "graph_iters": gi.value, "tune_us": list(tune)}
 
+    def tuning(self):
+        """The autotuner's classes (width class, size class, instances, vec,
+        items per wave, us per batched iteration) and each instance's class."""
+        nc = C.c_int32()
+        check(_lib.load().cc_batch_tuning(self._h, 0, C.byref(nc), None, None, None))
+        k = nc.value
+        cls = (C.c_int32 * max(5 * k, 1))()
+        us = (C.c_double * max(k, 1))()
+        inst = (C.c_int32 * max(len(self.problems), 1))()
+        check(_lib.load().cc_batch_tuning(self._h, k, C.byref(nc), cls, us, inst))
+        names = ("width_class", "size_class", "instances", "vec", "items_per_wave")
+        out = [{**{nm: cls[5 * c + q] for q, nm in enumerate(names)}, "us_per_iteration": us[c]} for c in range(k)]
+        return out, [inst[b] for b in range(len(self.problems))]
+
     def run(self, labels: bool = True):
         """Returns (labels, infos, latency_ms): labels[b] is an (n_gamma[b], n_b)
         int32 tensor (or None), infos[b] a list of per-gamma dicts,

@@ -3,6 +3,7 @@
 // ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -229,11 +230,36 @@ cc_status cc_batch_config(cc_batch_t batch, int32_t *vec, int32_t *items_per_wav
   CC_GUARD_BEGIN
   if (!batch) { set_error("batch is NULL"); return CC_ERR_INVALID_ARG; }
   const Batch *B = reinterpret_cast<const Batch *>(batch);
-  if (vec) *vec = B->ls.vec;
-  if (items_per_wave) *items_per_wave = B->ls.ipw;
+  // the instance with the most work (first in the block tables) and its class
+  const int b0 = B->order.empty() ? 0 : B->order[0];
+  if (vec) *vec = B->inst_vec.empty() ? 0 : B->inst_vec[b0];
+  if (items_per_wave) *items_per_wave = B->inst_ipw.empty() ? 0 : B->inst_ipw[b0];
   if (graph_iters) *graph_iters = B->graph_iters;
-  if (tune_us)
-    for (int c = 0; c < 9; ++c) tune_us[c] = c < (int)B->tune_us.size() ? B->tune_us[c] : 0.0;
+  if (tune_us) {
+    const TuneClass *tc = nullptr;
+    if (!B->inst_class.empty() && B->inst_class[b0] >= 0) tc = &B->classes[B->inst_class[b0]];
+    for (int c = 0; c < 9; ++c) tune_us[c] = (tc && c < (int)tc->tried.size()) ? tc->tried[c] : 0.0;
+  }
+  return CC_OK;
+  CC_GUARD_END
+}
+
+cc_status cc_batch_tuning(cc_batch_t batch, int32_t cap, int32_t *n_classes, int32_t *classes,
+                          double *us, int32_t *inst_class) {
+  CC_GUARD_BEGIN
+  if (!batch) { set_error("batch is NULL"); return CC_ERR_INVALID_ARG; }
+  if (cap < 0 || (cap > 0 && !classes)) { set_error("need cap >= 0 and classes for cap > 0"); return CC_ERR_INVALID_ARG; }
+  const Batch *B = reinterpret_cast<const Batch *>(batch);
+  const int nc = (int)B->classes.size();
+  if (n_classes) *n_classes = nc;
+  for (int c = 0; c < std::min(nc, (int)cap); ++c) {
+    const TuneClass &t = B->classes[c];
+    int32_t *o = classes + 5 * c;
+    o[0] = t.width; o[1] = t.size; o[2] = t.instances; o[3] = t.vec; o[4] = t.ipw;
+    if (us) us[c] = t.us;
+  }
+  if (inst_class)
+    for (size_t b = 0; b < B->probs.size(); ++b) inst_class[b] = B->inst_class.empty() ? -1 : B->inst_class[b];
   return CC_OK;
   CC_GUARD_END
 }

@@ -75,6 +75,8 @@ struct Problem {
   int tile_w = 256;   // features per tile (64 lanes x vec)
   int vec = 4;
   int ipw = 1;        // about this many items per wave in the point and item edge sweeps
+  int pwaves = kPointWaves;  // waves per block of the point sweep
+  int eipw = 1;       // about this many items per wave in the item edge sweep
   int entile = 1;     // edge-sweep tiles (1: the fused edge kernel)
   int npass = 4;      // 64-feature passes per edge tile
   bool efused = true;
@@ -141,22 +143,34 @@ struct Problem {
 struct PointArgs;  // kernel argument blocks (solver.hip)
 struct EdgeArgs;
 
-// Launch tables of problems that share launches: one point-sweep launch
-// (tile width 64 * vec) and one item edge-sweep launch per features-per-lane
-// class; block -> (instance, local block) tables and per-instance argument
-// blocks for both scalar-slot parities.
+// Launch tables of problems that share launches: one point-sweep launch per
+// class of (features per lane, items per wave) and one item edge-sweep
+// launch per features-per-lane class of the edge sweep; block -> (instance,
+// local block) tables and per-instance argument blocks for both scalar-slot
+// parities.  The classes cover disjoint instances.
+struct PointClass {
+  int vec = 4, ipw = 1, nblk = 0;
+  PointArgs *pargs[2] = {nullptr, nullptr};
+  int2 *ptab = nullptr;
+};
 struct EdgeClass {
   int nv = 1, nblk = 0;
   EdgeArgs *eargs[2] = {nullptr, nullptr};
   int2 *etab = nullptr;
 };
 struct LaunchSet {
-  int vec = 4;                    // point-sweep features per lane (all instances)
-  int ipw = 1;                    // about this many items per wave in both sweeps
-  int nblk_point = 0;
-  PointArgs *pargs[2] = {nullptr, nullptr};
-  int2 *ptab = nullptr;
+  std::vector<PointClass> pcls;
   std::vector<EdgeClass> ecls;
+};
+
+// Autotuner: instances are grouped by the width of their rows (p <= 64,
+// <= 128, <= 256, wider) and the number of point-sweep work items at their
+// natural tile width (<= 512, <= 2048, more); each group gets its own
+// (features per lane, items per wave).
+struct TuneClass {
+  int width = 0, size = 0, instances = 0, vec = 4, ipw = 1;
+  double us = 0.0;                // us per batched iteration with the choice
+  std::vector<double> tried;      // us for the 9 candidates (in order)
 };
 
 // Many problems solved along their own gamma paths in the same launches.
@@ -167,7 +181,7 @@ struct Batch {
   int graph_iters = 32;           // MM iterations per graph replay (even)
   cc_solve_opts opts{};
   hipStream_t stream = nullptr;   // private: graphs are captured on it
-  std::vector<hipStream_t> side;  // edge classes beyond the first, as graph branches
+  std::vector<hipStream_t> side;  // point and edge classes beyond the first, as graph branches
   std::vector<hipEvent_t> ev;      // fork and join events of those branches
   std::vector<int> order;         // instances by decreasing work
   BatchInst *bi = nullptr;
@@ -186,7 +200,9 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   double tick_khz = 100000.0;     // wall-clock counter rate
-  std::vector<double> tune_us;    // autotuner: us per iteration for vec = 1, 2, 4
+  std::vector<int> inst_vec, inst_ipw;  // per instance: point-sweep tile shape
+  std::vector<int> inst_class;    // per instance: its autotuner class
+  std::vector<TuneClass> classes; // autotuner classes (empty without autotuning)
 };
 
 // ---- error reporting (thread-local message) ----

@@ -525,13 +525,13 @@ __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, co
 // first sweep's A (the state type), a gather copy of its increment A - A'
 // (T0) and h_i (FP64, H); k_jacobi runs the other sweeps and the terms of d
 // that involve the final A (||U - A||^2, the A window and sum_i <h_i, a_i>).
-template <int PREC, int VEC, bool PF, bool BATCH, bool JAC = false>
+template <int PREC, int VEC, bool PF, bool BATCH, bool JAC = false, int NW = kPointWaves>
 __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   using TS = typename Traits<PREC>::TS;
   using TG = typename Traits<PREC>::TG;
   using TX = typename Traits<PREC>::TX;
-  __shared__ double scratch[kPointWaves * kPointSums];
-  __shared__ double red[(kPointWaves + 1) * kIterSums];
+  __shared__ double scratch[NW * kPointSums];
+  __shared__ double red[(NW + 1) * kIterSums];
   const TX *X = reinterpret_cast<const TX *>(a.X);
   TS *U = reinterpret_cast<TS *>(a.U);
   const int lane = threadIdx.x % kWave;
@@ -581,7 +581,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   };
   if (first < it1) preload(first, a.M != nullptr);
 
-  const DevScalars hs = begin_iteration<kPointWaves, BATCH>(a, red, blk);
+  const DevScalars hs = begin_iteration<NW, BATCH>(a, red, blk);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
   const bool needU = a.M != nullptr || m == 0;
@@ -601,7 +601,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
   double ps[kPointSums] = {0, 0, 0, 0, 0, 0};
 
-  for (int item = first; item < it1; item += kPointWaves) {
+  for (int item = first; item < it1; item += NW) {
     const int t = item / a.n, i = item - t * a.n;
     const int f0 = t * W + lane * VEC;
     const bool active = f0 < a.ld;
@@ -637,7 +637,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     RawIO<TG, VEC>::load(Gp + rowc, gr);
     if constexpr (PF && VEC == 4) NtIO<TS, 4>::load(Ap + rowc, apr);
     else RawIO<TS, VEC>::load(Ap + rowc, apr);
-    if (PF && item + kPointWaves < it1) preload(item + kPointWaves, needU);
+    if (PF && item + NW < it1) preload(item + NW, needU);
     double sumg[VEC], sumcg[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) sumg[v] = sumcg[v] = 0.0;
@@ -781,7 +781,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
         VecIO<VEC>::store(U + row, u);
         VecIO<VEC>::store(An + row, an);
       }
-      if (!JAC && Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, gn);
+      if constexpr (!JAC && Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, gn);
       if (winU) {
         double us[VEC];
         VecIO<VEC>::load(Us + row, us);
@@ -811,10 +811,11 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   }
 }
 
-// PF: prefetch each next item (for waves with several items).
-template <int PREC, int VEC, bool PF>
-__global__ __launch_bounds__(kPointBlock) void k_point(PointArgs a) {
-  point_sweep<PREC, VEC, PF, false>(a, hw_blk());
+// PF: prefetch each next item (for waves with several items).  NW waves
+// per block.
+template <int PREC, int VEC, bool PF, int NW = kPointWaves>
+__global__ __launch_bounds__(kWave * NW) void k_point(PointArgs a) {
+  point_sweep<PREC, VEC, PF, false, false, NW>(a, hw_blk());
 }
 
 // First sweep of several (proj_sweeps > 1): the same launch as k_point.
@@ -1867,6 +1868,21 @@ static void launch_point_t(Problem *P, const Launch &Lp) {
               point_args(P, Lp));
     return;
   }
+  // wider blocks: the mixed precision with 4 features per lane
+  if constexpr (PREC == kMixed && VEC == 4) {
+    if (P->pwaves == 8 || P->pwaves == 16) {
+      const bool pf = Lp.chunk > P->pwaves;
+      const dim3 t(kWave * P->pwaves);
+      if (P->pwaves == 8) {
+        if (pf) klaunch(k_point<PREC, VEC, true, 8>, dim3(Lp.blocks), t, 0, P->stream, P->pev[0], P->pev[1], point_args(P, Lp));
+        else klaunch(k_point<PREC, VEC, false, 8>, dim3(Lp.blocks), t, 0, P->stream, P->pev[0], P->pev[1], point_args(P, Lp));
+      } else {
+        if (pf) klaunch(k_point<PREC, VEC, true, 16>, dim3(Lp.blocks), t, 0, P->stream, P->pev[0], P->pev[1], point_args(P, Lp));
+        else klaunch(k_point<PREC, VEC, false, 16>, dim3(Lp.blocks), t, 0, P->stream, P->pev[0], P->pev[1], point_args(P, Lp));
+      }
+      return;
+    }
+  }
   // prefetching pays when a wave has more than one item
   if (Lp.chunk > kPointWaves)
     klaunch(k_point<PREC, VEC, true>, dim3(Lp.blocks), dim3(kPointBlock), 0, P->stream, P->pev[0], P->pev[1],
@@ -1921,14 +1937,14 @@ static int edge_reduce_blocks(int64_t E) {
 
 // Partial rows the edge stage leaves for the next point sweep.
 static int edge_rows(Problem *P) {
-  if (P->eitems) return edge_items_grid(P->n_items, P->ipw).blocks;
+  if (P->eitems) return edge_items_grid(P->n_items, P->eipw).blocks;
   return P->efused ? edge_fused_grid(P->E).blocks : edge_reduce_blocks(P->E);
 }
 
 template <int PREC>
 static void launch_edge_p(Problem *P, int init, int nbp) {
   if (P->eitems) {
-    const Launch Li = edge_items_grid(P->n_items, P->ipw);
+    const Launch Li = edge_items_grid(P->n_items, P->eipw);
     const EdgeArgs ea = edge_args(P, Li, init, nbp);
     switch (P->item_nv) {
       case 1: klaunch(k_edge_items<PREC, 1>, dim3(Li.blocks), dim3(kEdgeBlock), 0, P->stream, P->pev[2], P->pev[3], ea); break;
@@ -1990,10 +2006,20 @@ static void set_slab_attr() {
   (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
 }
 
+// Waves per block of the point sweep's launch.
+static int point_waves(const Problem *P) {
+  return (P->psweeps == 1 && P->precision == kMixed && P->vec == 4) ? P->pwaves : kPointWaves;
+}
+
+// Grid of the point sweep.
+static Launch point_grid(const Problem *P) {
+  return sweep_grid(P->n * P->ntile, point_waves(P), P->ipw);
+}
+
 // Blocks of the point sweep (its partials count).
 static int point_blocks(Problem *P) {
   if (P->slab_f > 0) return (int)(cdiv(P->ntile * cdiv(P->n, kBlock), kXcds) * kXcds);
-  return sweep_grid(P->n * P->ntile, kPointWaves, P->ipw).blocks;
+  return point_grid(P).blocks;
 }
 
 template <int PREC>
@@ -2020,7 +2046,7 @@ static void launch_point_p(Problem *P, const Launch &Lp) {
 static void launch_iteration(Problem *P) {
   hipEvent_t *ev = prof_slot(P);
   for (int q = 0; q < 4; ++q) P->pev[q] = ev ? ev[q] : nullptr;
-  const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves, P->ipw);
+  const Launch Lp = point_grid(P);
   const int nbp = point_blocks(P);
   if (P->precision == kF32) launch_point_p<kF32>(P, Lp);
   else if (P->precision == kF64) launch_point_p<kF64>(P, Lp);
@@ -2143,8 +2169,22 @@ static void choose_tiles(Problem *P) {
   const char *ei = getenv("CCMI_IPW");
   const int ipw = ei ? atoi(ei) : 1;
   P->ipw = (ipw == 2 || ipw == 4) ? ipw : 1;
+  // items per wave of the item edge sweep alone (CCMI_EDGE_IPW = 1, 2 or 4;
+  // default: as the point sweep)
+  const char *eiw = getenv("CCMI_EDGE_IPW");
+  const int eipw = eiw ? atoi(eiw) : P->ipw;
+  P->eipw = (eipw == 2 || eipw == 4) ? eipw : 1;
   P->tile_w = slab > 0 ? slab : kWave * vec;
   P->ntile = (int)cdiv(P->ld, P->tile_w);
+  // waves per block of the point sweep (CCMI_POINT_WAVES = 4, 8 or 16; the
+  // wider blocks for the mixed precision with 4 features per lane).  With
+  // several items per wave (more items than 4-wave blocks on the capped grid
+  // have waves) 8-wave blocks measured faster (genotype: 286 against 296 us),
+  // with one item per wave 4-wave blocks (expression: 24.2 against 25.3 us)
+  const char *pw = getenv("CCMI_POINT_WAVES");
+  const bool several = P->n * P->ntile > (int64_t)kMaxBlocks * kPointWaves;
+  const int pwv = pw ? atoi(pw) : (several ? 8 : kPointWaves);
+  P->pwaves = (pwv == 8 || pwv == 16) ? pwv : kPointWaves;
   // edge sweep: work items of edges sharing a lower end when the whole row
   // fits a wave at up to 16 features per lane (CCMI_EDGE_ITEMS=0 turns this
   // off), else one tile over the whole row when it is at most 1024 wide
@@ -2677,48 +2717,67 @@ __global__ void k_batch_done_ticks(int n_inst, const BatchInst *bi, unsigned lon
   if (b < n_inst) out[b] = *bi[b].t_done;
 }
 
-template <int PREC, bool PF>
-static void launch_set_point_pf(const LaunchSet &L, int par, hipStream_t st) {
-  const dim3 g(L.nblk_point), t(kPointBlock);
-  switch (L.vec) {
-    case 1: hipLaunchKernelGGL((k_point_batch<PREC, 1, PF>), g, t, 0, st, L.pargs[par], L.ptab); break;
-    case 2: hipLaunchKernelGGL((k_point_batch<PREC, 2, PF>), g, t, 0, st, L.pargs[par], L.ptab); break;
-    default: hipLaunchKernelGGL((k_point_batch<PREC, 4, PF>), g, t, 0, st, L.pargs[par], L.ptab); break;
+template <int PREC>
+static void launch_point_class(const PointClass &c, int par, hipStream_t st) {
+  const dim3 g(c.nblk), t(kPointBlock);
+  if (c.ipw > 1) {
+    switch (c.vec) {
+      case 1: hipLaunchKernelGGL((k_point_batch<PREC, 1, true>), g, t, 0, st, c.pargs[par], c.ptab); break;
+      case 2: hipLaunchKernelGGL((k_point_batch<PREC, 2, true>), g, t, 0, st, c.pargs[par], c.ptab); break;
+      default: hipLaunchKernelGGL((k_point_batch<PREC, 4, true>), g, t, 0, st, c.pargs[par], c.ptab); break;
+    }
+  } else {
+    switch (c.vec) {
+      case 1: hipLaunchKernelGGL((k_point_batch<PREC, 1, false>), g, t, 0, st, c.pargs[par], c.ptab); break;
+      case 2: hipLaunchKernelGGL((k_point_batch<PREC, 2, false>), g, t, 0, st, c.pargs[par], c.ptab); break;
+      default: hipLaunchKernelGGL((k_point_batch<PREC, 4, false>), g, t, 0, st, c.pargs[par], c.ptab); break;
+    }
   }
 }
 
-// One iteration of a launch set.  With side streams and events (graph
-// capture), edge classes after the first run on their own streams as
-// parallel branches between the point sweep and the next iteration: the
-// classes cover disjoint instances.
 template <int PREC>
-static void launch_set_p(const LaunchSet &L, int par, hipStream_t st, const hipStream_t *side,
-                         const hipEvent_t *ev) {
-  if (L.nblk_point > 0) {
-    if (L.ipw > 1) launch_set_point_pf<PREC, true>(L, par, st);
-    else launch_set_point_pf<PREC, false>(L, par, st);
+static void launch_edge_class(const EdgeClass &c, int par, hipStream_t s) {
+  const dim3 g(c.nblk), t(kEdgeBlock);
+  switch (c.nv) {
+    case 1: hipLaunchKernelGGL((k_edge_items_batch<PREC, 1>), g, t, 0, s, c.eargs[par], c.etab); break;
+    case 2: hipLaunchKernelGGL((k_edge_items_batch<PREC, 2>), g, t, 0, s, c.eargs[par], c.etab); break;
+    case 4: hipLaunchKernelGGL((k_edge_items_batch<PREC, 4>), g, t, 0, s, c.eargs[par], c.etab); break;
+    case 8: hipLaunchKernelGGL((k_edge_items_batch<PREC, 8>), g, t, 0, s, c.eargs[par], c.etab); break;
+    default: hipLaunchKernelGGL((k_edge_items_batch<PREC, 16>), g, t, 0, s, c.eargs[par], c.etab); break;
   }
-  const int nc = (int)L.ecls.size();
+}
+
+// Launches of one class list; with side streams and events (graph capture)
+// the classes after the first run on their own streams as parallel branches
+// forked from and joined back into st (they cover disjoint instances).
+template <typename Cls, typename Fn>
+static void launch_branches(const std::vector<Cls> &cls, hipStream_t st, const hipStream_t *side,
+                            const hipEvent_t *ev, Fn launch) {
+  const int nc = (int)cls.size();
   if (side && nc > 1) (void)hipEventRecord(ev[0], st);
   for (int k = 0; k < nc; ++k) {
-    const EdgeClass &c = L.ecls[k];
     hipStream_t s = st;
     if (side && k > 0) {
       s = side[k - 1];
       (void)hipStreamWaitEvent(s, ev[0], 0);
     }
-    const dim3 g(c.nblk), t(kEdgeBlock);
-    switch (c.nv) {
-      case 1: hipLaunchKernelGGL((k_edge_items_batch<PREC, 1>), g, t, 0, s, c.eargs[par], c.etab); break;
-      case 2: hipLaunchKernelGGL((k_edge_items_batch<PREC, 2>), g, t, 0, s, c.eargs[par], c.etab); break;
-      case 4: hipLaunchKernelGGL((k_edge_items_batch<PREC, 4>), g, t, 0, s, c.eargs[par], c.etab); break;
-      case 8: hipLaunchKernelGGL((k_edge_items_batch<PREC, 8>), g, t, 0, s, c.eargs[par], c.etab); break;
-      default: hipLaunchKernelGGL((k_edge_items_batch<PREC, 16>), g, t, 0, s, c.eargs[par], c.etab); break;
-    }
+    launch(cls[k], s);
     if (side && k > 0) (void)hipEventRecord(ev[k], s);
   }
   if (side)
     for (int k = 1; k < nc; ++k) (void)hipStreamWaitEvent(st, ev[k], 0);
+}
+
+// One iteration of a launch set: every point class, then every edge class.
+template <int PREC>
+static void launch_set_p(const LaunchSet &L, int par, hipStream_t st, const hipStream_t *side,
+                         const hipEvent_t *ev) {
+  launch_branches(L.pcls, st, side, ev, [&](const PointClass &c, hipStream_t s) {
+    if (c.nblk > 0) launch_point_class<PREC>(c, par, s);
+  });
+  launch_branches(L.ecls, st, side, ev, [&](const EdgeClass &c, hipStream_t s) {
+    launch_edge_class<PREC>(c, par, s);
+  });
 }
 
 // One MM iteration of every problem of the set (scalar-slot parity par).
@@ -2739,9 +2798,11 @@ static cc_status upload(T **dst, const std::vector<T> &v, hipStream_t st) {
 }
 
 static void free_launch_set(LaunchSet &L) {
-  void *bufs[] = {L.pargs[0], L.pargs[1], L.ptab};
-  for (void *b : bufs)
-    if (b) (void)hipFree(b);
+  for (PointClass &c : L.pcls) {
+    void *pb[] = {c.pargs[0], c.pargs[1], c.ptab};
+    for (void *b : pb)
+      if (b) (void)hipFree(b);
+  }
   for (EdgeClass &c : L.ecls) {
     void *eb[] = {c.eargs[0], c.eargs[1], c.etab};
     for (void *b : eb)
@@ -2751,28 +2812,28 @@ static void free_launch_set(LaunchSet &L) {
 }
 
 // Launch tables for problems probs[k] (device descriptors bis[k]), blocks
-// laid out in the given order of instances: tile shape vec and about ipw
-// items per wave (waves with several items prefetch the next) for every
-// instance, edge launches grouped by each instance's features per lane.
-// Sets the problems' tile fields and scalar slot 0.
+// laid out in the given order of instances: instance k gets tile shape
+// vec_of[k] (64 * vec features per wave) and about ipw_of[k] items per wave
+// (waves with several items prefetch the next); point launches are grouped
+// by (vec, ipw), edge launches by each instance's features per lane.  Sets
+// the problems' tile fields and scalar slot 0.
 static cc_status build_launch_set(LaunchSet &L, const std::vector<Problem *> &probs,
                                   const std::vector<const BatchInst *> &bis,
-                                  const std::vector<int> &order, int vec, int ipw, int K,
-                                  hipStream_t st) {
+                                  const std::vector<int> &order, const std::vector<int> &vec_of,
+                                  const std::vector<int> &ipw_of, int K, hipStream_t st) {
   free_launch_set(L);
-  L.vec = vec;
-  L.ipw = ipw;
   const int n_inst = (int)probs.size();
   std::vector<PointArgs> pa[2];
   std::vector<EdgeArgs> ea[2];
   std::vector<int> pblocks(n_inst), eblocks(n_inst);
   for (int b = 0; b < n_inst; ++b) {
     Problem *P = probs[b];
-    P->vec = vec;
-    P->tile_w = kWave * vec;
+    P->vec = vec_of[b];
+    P->tile_w = kWave * P->vec;
     P->ntile = (int)cdiv(P->ld, P->tile_w);
     P->cur_K = K;
-    P->ipw = ipw;
+    P->ipw = ipw_of[b];
+    P->eipw = ipw_of[b];
     P->nbe = edge_rows(P);
     const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves, P->ipw);
     const Launch Li = edge_items_grid(P->n_items, P->ipw);
@@ -2788,12 +2849,25 @@ static cc_status build_launch_set(LaunchSet &L, const std::vector<Problem *> &pr
     }
     P->slot = 0;
   }
-  std::vector<int2> pt;
-  for (int b : order)
-    for (int q = 0; q < pblocks[b]; ++q) pt.push_back(make_int2(b, q));
-  L.nblk_point = (int)pt.size();
-  for (int par = 0; par < 2; ++par) CC_TRY(upload(&L.pargs[par], pa[par], st));
-  CC_TRY(upload(&L.ptab, pt, st));
+  // point classes in order of first appearance along the instance order
+  std::vector<std::pair<int, int>> keys;
+  for (int b : order) {
+    const std::pair<int, int> k{vec_of[b], ipw_of[b]};
+    if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+  }
+  for (const auto &k : keys) {
+    std::vector<int2> pt;
+    for (int b : order)
+      if (vec_of[b] == k.first && ipw_of[b] == k.second)
+        for (int q = 0; q < pblocks[b]; ++q) pt.push_back(make_int2(b, q));
+    PointClass c;
+    c.vec = k.first;
+    c.ipw = k.second;
+    c.nblk = (int)pt.size();
+    for (int par = 0; par < 2; ++par) CC_TRY(upload(&c.pargs[par], pa[par], st));
+    CC_TRY(upload(&c.ptab, pt, st));
+    L.pcls.push_back(c);
+  }
   for (int nv : {1, 2, 4, 8, 16}) {
     std::vector<int2> et;
     for (int b : order)
@@ -2811,17 +2885,18 @@ static cc_status build_launch_set(LaunchSet &L, const std::vector<Problem *> &pr
   return CC_OK;
 }
 
-// Launch tables and the graph of graph_iters iterations for (vec, ipw).
-static cc_status batch_configure(Batch *B, int vec, int ipw, const std::vector<int> *order = nullptr) {
+// Launch tables and the graph of graph_iters iterations for the instances'
+// tile shapes (inst_vec, inst_ipw), over the given instances (default all).
+static cc_status batch_configure(Batch *B, const std::vector<int> *order = nullptr) {
   std::vector<const BatchInst *> bis;
   for (size_t b = 0; b < B->probs.size(); ++b) bis.push_back(B->bi + b);
-  CC_TRY(build_launch_set(B->ls, B->probs, bis, order ? *order : B->order, vec, ipw, B->opts.test_every,
-                          B->stream));
+  CC_TRY(build_launch_set(B->ls, B->probs, bis, order ? *order : B->order, B->inst_vec, B->inst_ipw,
+                          B->opts.test_every, B->stream));
   if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   B->gexec = nullptr;
   B->graph = nullptr;
-  const size_t nc = B->ls.ecls.size();
+  const size_t nc = std::max(B->ls.ecls.size(), B->ls.pcls.size());
   while (B->side.size() + 1 < nc) {
     hipStream_t s;
     CC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -2859,6 +2934,9 @@ static cc_status batch_start(Batch *B) {
 
 // Autotuner candidates: (vec, items per wave) = (1,1), (1,4), (1,16), (2,1), ...
 constexpr int kTuneConfigs = 9;
+// Features per lane of a batched point sweep without tuning: the whole row
+// in one wave where it fits.
+static int natural_vec(int64_t ld) { return ld > 128 ? 4 : (ld > 64 ? 2 : 1); }
 static int tune_vec(int c) { return 1 << (c / 3); }
 static int tune_ipw(int c) { return c % 3 == 0 ? 1 : (c % 3 == 1 ? 4 : 16); }
 
@@ -2992,28 +3070,66 @@ cc_status batch_create(int32_t n_inst, Problem *const *probs, const int32_t *n_g
            probs[b]->n * probs[b]->ld + 2 * probs[b]->E * probs[b]->ld;
   });
 
+  // the tile shape a single solve would take: 64 * vec features per wave
+  // with vec from the row width, one item per wave
+  B->inst_vec.resize(n_inst);
+  B->inst_ipw.assign(n_inst, 1);
+  B->inst_class.assign(n_inst, -1);
+  for (int b = 0; b < n_inst; ++b) B->inst_vec[b] = natural_vec(probs[b]->ld);
   if (autotune) {
-    // point-sweep tile widths 64, 128 and 256 features, each with 1, 4 and
-    // 16 items per wave: time a few graph replays of each from the
-    // instances' initial states and keep the fastest
-    double best = 1e300;
-    int best_c = 0;
-    B->tune_us.assign(kTuneConfigs, 0.0);
-    for (int c = 0; c < kTuneConfigs; ++c) {
-      for (Problem *P : B->probs) CC_TRY(reset_state(P));
-      CC_TRY(batch_configure(B, tune_vec(c), tune_ipw(c)));
-      double us = 0.0;
-      CC_TRY(batch_time(B, 2, &us));
-      B->tune_us[c] = us;
-      if (us < best) { best = us; best_c = c; }
+    // classes by row width and point-sweep work; per class, coordinate
+    // descent over (vec, items per wave) in {1, 2, 4} x {1, 4, 16}: each
+    // candidate is timed over a few graph replays of the whole batch from
+    // the initial states, the others keeping their current choice; classes
+    // with more work are tuned first
+    std::vector<int> wsum;
+    for (int b = 0; b < n_inst; ++b) {
+      const Problem *P = probs[b];
+      const int width = P->ld <= 64 ? 0 : (P->ld <= 128 ? 1 : (P->ld <= 256 ? 2 : 3));
+      const int64_t items = P->n * cdiv(P->ld, kWave * B->inst_vec[b]);
+      const int size = items <= 512 ? 0 : (items <= 2048 ? 1 : 2);
+      int c = -1;
+      for (size_t k = 0; k < B->classes.size(); ++k)
+        if (B->classes[k].width == width && B->classes[k].size == size) c = (int)k;
+      if (c < 0) {
+        TuneClass tc;
+        tc.width = width;
+        tc.size = size;
+        B->classes.push_back(tc);
+        wsum.push_back(0);
+        c = (int)B->classes.size() - 1;
+      }
+      B->classes[c].instances += 1;
+      wsum[c] += (int)std::min<int64_t>(P->n * P->ld + 2 * P->E * P->ld, 1 << 30);
+      B->inst_class[b] = c;
+    }
+    std::vector<int> cord(B->classes.size());
+    std::iota(cord.begin(), cord.end(), 0);
+    std::stable_sort(cord.begin(), cord.end(), [&](int a, int b) { return wsum[a] > wsum[b]; });
+    for (int c : cord) {
+      TuneClass &tc = B->classes[c];
+      tc.tried.assign(kTuneConfigs, 0.0);
+      double best = 1e300;
+      int best_k = 0;
+      for (int k = 0; k < kTuneConfigs; ++k) {
+        for (int b = 0; b < n_inst; ++b)
+          if (B->inst_class[b] == c) { B->inst_vec[b] = tune_vec(k); B->inst_ipw[b] = tune_ipw(k); }
+        for (Problem *P : B->probs) CC_TRY(reset_state(P));
+        CC_TRY(batch_configure(B));
+        double us = 0.0;
+        CC_TRY(batch_time(B, 2, &us));
+        tc.tried[k] = us;
+        if (us < best) { best = us; best_k = k; }
+      }
+      tc.vec = tune_vec(best_k);
+      tc.ipw = tune_ipw(best_k);
+      tc.us = best;
+      for (int b = 0; b < n_inst; ++b)
+        if (B->inst_class[b] == c) { B->inst_vec[b] = tc.vec; B->inst_ipw[b] = tc.ipw; }
     }
     for (Problem *P : B->probs) CC_TRY(reset_state(P));
-    CC_TRY(batch_configure(B, tune_vec(best_c), tune_ipw(best_c)));
-  } else {
-    int64_t maxld = 0;
-    for (Problem *P : B->probs) maxld = std::max<int64_t>(maxld, P->ld);
-    CC_TRY(batch_configure(B, maxld > 128 ? 4 : (maxld > 64 ? 2 : 1), 1));
   }
+  CC_TRY(batch_configure(B));
   guard.ok = true;
   *out = B;
   return CC_OK;
@@ -3068,14 +3184,14 @@ cc_status batch_run(Batch *B, int32_t *labels, cc_solve_info *infos, double *lat
       for (int b : B->order)
         if (!hfin[b]) active.push_back(b);
       if (!active.empty()) {
-        CC_TRY(batch_configure(B, B->ls.vec, B->ls.ipw, &active));
+        CC_TRY(batch_configure(B, &active));
         in_set = (int)active.size();
         compacted = true;
       }
     }
   }
   // the next run starts from the full tables
-  if (compacted) CC_TRY(batch_configure(B, B->ls.vec, B->ls.ipw));
+  if (compacted) CC_TRY(batch_configure(B));
   if (!finished) { set_error("batch did not finish within its iteration caps"); return CC_ERR_STATE; }
   // graph_iters is even: every instance is back on scalar slot 0
   std::vector<double> hinfo(B->total_gamma * kInfoVals);
@@ -3352,7 +3468,8 @@ cc_status server_step(Server *S, int32_t *n_active, int32_t *n_waiting, int32_t 
       std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return probs[a]->n * probs[a]->ld > probs[b]->n * probs[b]->ld;
       });
-      CC_TRY(build_launch_set(S->ls, probs, bis, order, S->vec, S->ipw, S->opts.test_every, S->stream));
+      CC_TRY(build_launch_set(S->ls, probs, bis, order, std::vector<int>(na, S->vec),
+                              std::vector<int>(na, S->ipw), S->opts.test_every, S->stream));
       CC_HIP(hipMemcpyAsync(S->d_sc0, sc0.data(), sc0.size() * sizeof(DevScalars *), hipMemcpyHostToDevice, S->stream));
       S->dirty = false;
     }

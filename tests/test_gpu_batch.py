@@ -73,6 +73,15 @@ def test_batch_mixed_shapes_autotuned(cc):
         cfg = bt.config()
         assert cfg["vec"] in (1, 2, 4) and cfg["items_per_wave"] in (1, 4, 16)
         assert len(cfg["tune_us"]) == 9 and all(t > 0 for t in cfg["tune_us"])
+        classes, of = bt.tuning()
+        # one class per (row width, work) group; every instance in exactly one
+        assert sum(c["instances"] for c in classes) == len(ids)
+        assert sorted(set(of)) == list(range(len(classes)))
+        for c in classes:
+            assert c["vec"] in (1, 2, 4) and c["items_per_wave"] in (1, 4, 16) and c["us_per_iteration"] > 0
+        for b, (X, *_rest) in enumerate(inst):
+            p = X.shape[1]
+            assert classes[of[b]]["width_class"] == (0 if p <= 64 else 1 if p <= 128 else 2 if p <= 256 else 3)
         labs, infos, lat = bt.run()
     for b, (pr, (rinf, rlab, rU, rA, rs)) in enumerate(zip(probs, ref)):
         U = pr.get_state()[0].cpu().numpy()

@@ -183,12 +183,13 @@ def test_genotype_full_repeat_is_bitwise(cc, genotype):
 
 def test_batched_full_size_sampled_instances_equal_alone(cc, monkeypatch):
     """The bench's batched configuration: 256 instances of the batched recipe
-    with 16 gammas each (tol 1e-4, at most 5000 iterations per gamma),
-    autotuned.  Sampled instances solved alone with the chosen tile shape
-    give the same labels, infos and final state, bitwise when the chosen
-    items per wave can be asked of a single solve (1 or 4), else within the
-    solver's 1e-5 bar with the same labels for converged gammas."""
-    opts = dict(max_iter=5000, tol=1e-4)
+    with 16 gammas each (tol 1e-4, at most 2000 iterations per gamma),
+    autotuned per class of instances.  Sampled instances solved alone with
+    their class's tile shape give the same labels, infos and final state,
+    bitwise when the chosen items per wave can be asked of a single solve
+    (1 or 4), else within the solver's 1e-5 bar with the same labels for
+    converged gammas."""
+    opts = dict(max_iter=2000, tol=1e-4)
 
     def make(b):
         wl = gen.batched_instance(b)
@@ -198,17 +199,18 @@ def test_batched_full_size_sampled_instances_equal_alone(cc, monkeypatch):
 
     inst = [make(b) for b in range(256)]
     with cc.Batch([p for p, _ in inst], [g for _, g in inst], autotune=True, **opts) as bt:
-        cfg = bt.config()
+        classes, of = bt.tuning()
         labs, infos, lat = bt.run(labels=True)
     assert np.all(lat > 0)
+    assert len(classes) > 1 and sum(c["instances"] for c in classes) == 256
     states = {b: [t.cpu().numpy() for t in inst[b][0].get_state()] for b in (0, 77, 150, 255)}
     for p, _ in inst:
         p.close()
-    monkeypatch.setenv("CCMI_VEC", str(cfg["vec"]))
-    exact = cfg["items_per_wave"] in (1, 4)
-    if exact:
-        monkeypatch.setenv("CCMI_IPW", str(cfg["items_per_wave"]))
     for b, (U, A, s) in states.items():
+        cfg = classes[of[b]]
+        monkeypatch.setenv("CCMI_VEC", str(cfg["vec"]))
+        exact = cfg["items_per_wave"] in (1, 4)
+        monkeypatch.setenv("CCMI_IPW", str(cfg["items_per_wave"] if exact else 1))
         p, g = make(b)
         with p:
             rinf, rlab, _ = p.solve_path(g, labels=True, **opts)

@@ -471,3 +471,17 @@ def test_non_finite_state_reports_numeric_error(cc):
         g.reset_state()
         g.solve(10.0, tol=0.0, max_iter=50)
         assert np.array_equal(g.U(torch.float64).cpu().numpy(), Uref)
+
+
+def test_point_sweep_prefetch_mixed_wide_blocks(cc):
+    """The mixed precision with several items per wave (3000 points x 3
+    tiles) runs the point sweep in 8-wave blocks: trajectory within the
+    mixed bar with the same fused edges."""
+    X, M, E, w, _ = reduced_expression(n=3000, p=700)
+    st, _ = oracle_jacobi(X, M, E, w).solve(5.0, mm.Opts(tol=0, max_iter=12, proj="jacobi:1"))
+    with _gpu(cc, X, M, E, w, "mixed") as g:
+        g.solve(5.0, tol=0.0, max_iter=12)
+        U, A, s = (t.cpu().numpy() for t in g.get_state())
+    assert rel_max(U, st.U) < 2e-6
+    assert rel_max(A, st.A) < 2e-6
+    assert np.array_equal(s == 0, st.s == 0)
