@@ -84,6 +84,7 @@ struct Problem {
   int item_nv = 8;           // features per lane of the item edge sweep
   int64_t n_items = 0;       // edge work items (up to kItemEdges edges each)
   bool eslab = false;        // wide rows, small n: LDS-slab edge sweep
+  bool eslab_items = false;  // the slab sweep takes edges in work items
   int eslab_tpg = 1;         // feature tiles per block of the slab edge sweep
   int eslab_ntf = 1;         // feature tiles of width edge_f
   int edge_f = 0;            // LDS tile width of the slab edge sweep

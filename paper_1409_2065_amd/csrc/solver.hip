@@ -1501,11 +1501,17 @@ __global__ __launch_bounds__(kBlock) void k_edge_tiles(EdgeArgs a) {
 // writes one partial per (edge, group) for k_edge_reduce.
 constexpr int kEdgesPerThread = 16;
 constexpr int kSlabChunks = 4;  // staged four-feature chunks per thread and tile
+// LDS row stride of the slab edge sweeps: F + 4 elements.  The sweeps read
+// rows at random; a stride of 16 floats would start every row in one of two
+// bank groups, the padded stride spreads rows over all of them and keeps the
+// 16-byte alignment of four-element reads.
+constexpr int kSlabPad = 4;
 
 template <int PREC, int F>
 __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_group, int ntiles_f) {
   using TG = typename Traits<PREC>::TG;
   constexpr int C4 = F / 4;
+  constexpr int RS = F + kSlabPad;
   extern __shared__ __align__(16) unsigned char smem[];
   TG *slab = reinterpret_cast<TG *>(smem);
   const DevScalars *sc = a.sc;
@@ -1550,7 +1556,7 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
       const int idx = threadIdx.x + q * 1024;
       if (idx < nch) {
         const int row = idx / C4, c = idx - row * C4;
-        TG *dst = slab + (size_t)row * F + 4 * c;
+        TG *dst = slab + (size_t)row * RS + 4 * c;
         dst[0] = nv[q][0]; dst[1] = nv[q][1]; dst[2] = nv[q][2]; dst[3] = nv[q][3];
       }
     }
@@ -1559,8 +1565,8 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
     for (int u = 0; u < kEdgesPerThread; ++u) {
       const int e = threadIdx.x + u * blockDim.x;
       if (e < E) {
-        const TG *ri = slab + (size_t)(eij[u] >> 16) * F;
-        const TG *rj = slab + (size_t)(eij[u] & 0xffffu) * F;
+        const TG *ri = slab + (size_t)(eij[u] >> 16) * RS;
+        const TG *rj = slab + (size_t)(eij[u] & 0xffffu) * RS;
 #pragma unroll
         for (int f = 0; f < F; ++f) {
           const double d = (double)ri[f] - (double)rj[f];
@@ -1578,6 +1584,119 @@ __global__ __launch_bounds__(1024) void k_edge_slab(EdgeArgs a, int tiles_per_gr
   for (int u = 0; u < kEdgesPerThread; ++u) {
     const int e = threadIdx.x + u * blockDim.x;
     if (e < E) a.part[(size_t)e * a.ntile + g] = acc[u];
+  }
+}
+
+// Wide rows with small n, edges grouped into work items (edges sharing their
+// lower end i, as for the item edge sweep): as k_edge_slab, but each thread
+// takes up to kSlabItemSlots items, reads and converts the tile of row i from
+// LDS once per item and then only the rows j of its edges: per edge-feature
+// one LDS read and three operations instead of two and four.  Each edge's
+// partial is the same sum in the same order as in k_edge_slab.
+constexpr int kSlabItemSlots = 3;
+
+template <int PREC, int F>
+__global__ __launch_bounds__(1024) void k_edge_slab_items(EdgeArgs a, int tiles_per_group, int ntiles_f) {
+  using TG = typename Traits<PREC>::TG;
+  constexpr int C4 = F / 4;
+  constexpr int RS = F + kSlabPad;
+  extern __shared__ __align__(16) unsigned char smem[];
+  TG *slab = reinterpret_cast<TG *>(smem);
+  const DevScalars *sc = a.sc;
+  if (!a.init && sc->done) return;
+  const int pa = sc->pa;
+  const int buf = a.init ? pa : (pa ^ 1);
+  const TG *Gc = reinterpret_cast<const TG *>(buf == 0 ? a.G0 : a.G1);
+  const int g = hw_blk().lb;
+  const int t0 = g * tiles_per_group, t1 = min(t0 + tiles_per_group, ntiles_f);
+  // the items of this thread: lower end (-1: none) and the upper ends in
+  // 16-bit halves (0xffff: unused slot; the slab holds n < 2^16 rows)
+  int ii[kSlabItemSlots];
+  uint32_t jj[kSlabItemSlots][kItemEdges / 2];
+  double acc[kSlabItemSlots][kItemEdges];
+#pragma unroll
+  for (int u = 0; u < kSlabItemSlots; ++u) {
+    const int it = threadIdx.x + u * 1024;
+    ii[u] = -1;
+#pragma unroll
+    for (int h = 0; h < kItemEdges / 2; ++h) jj[u][h] = 0xffffffffu;
+#pragma unroll
+    for (int q = 0; q < kItemEdges; ++q) acc[u][q] = 0.0;
+    if (it < a.nitems) {
+      ii[u] = a.itemI[it];
+#pragma unroll
+      for (int h = 0; h < kItemEdges / 2; ++h) {
+        const int j0 = a.itemJ[(size_t)it * kItemEdges + 2 * h];
+        const int j1 = a.itemJ[(size_t)it * kItemEdges + 2 * h + 1];
+        jj[u][h] = (j0 >= 0 ? (uint32_t)j0 : 0xffffu) | ((j1 >= 0 ? (uint32_t)j1 : 0xffffu) << 16);
+      }
+    }
+  }
+  const int nch = a.n * C4;
+  TG nv[kSlabChunks][4];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int q = 0; q < kSlabChunks; ++q) {
+      const int idx = threadIdx.x + q * 1024;
+      const int row = idx / C4, c = idx - row * C4;
+      const int f = t * F + 4 * c;
+      nv[q][0] = nv[q][1] = nv[q][2] = nv[q][3] = (TG)0;
+      if (idx < nch && f < a.ld) RawIO<TG, 4>::load(Gc + (size_t)row * a.ld + f, nv[q]);
+    }
+  };
+  for (int t = t0; t < t1; ++t) {
+    fetch(t);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSlabChunks; ++q) {
+      const int idx = threadIdx.x + q * 1024;
+      if (idx < nch) {
+        const int row = idx / C4, c = idx - row * C4;
+        TG *dst = slab + (size_t)row * RS + 4 * c;
+        dst[0] = nv[q][0]; dst[1] = nv[q][1]; dst[2] = nv[q][2]; dst[3] = nv[q][3];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSlabItemSlots; ++u) {
+      if (ii[u] >= 0) {
+        const TG *ri = slab + (size_t)ii[u] * RS;
+        // four features of row i at a time; each edge still adds its
+        // features in ascending order
+#pragma unroll
+        for (int f0 = 0; f0 < F; f0 += 4) {
+          const double x0 = (double)ri[f0], x1 = (double)ri[f0 + 1];
+          const double x2 = (double)ri[f0 + 2], x3 = (double)ri[f0 + 3];
+#pragma unroll
+          for (int q = 0; q < kItemEdges; ++q) {
+            const uint32_t j = (jj[u][q / 2] >> (16 * (q % 2))) & 0xffffu;
+            if (j != 0xffffu) {
+              const TG *rj = slab + (size_t)j * RS + f0;
+              double d = x0 - (double)rj[0];
+              acc[u][q] = fma(d, d, acc[u][q]);
+              d = x1 - (double)rj[1];
+              acc[u][q] = fma(d, d, acc[u][q]);
+              d = x2 - (double)rj[2];
+              acc[u][q] = fma(d, d, acc[u][q]);
+              d = x3 - (double)rj[3];
+              acc[u][q] = fma(d, d, acc[u][q]);
+            }
+          }
+        }
+      }
+    }
+  }
+  const bool pad = g * tiles_per_group >= ntiles_f;  // a padding block owns no tiles
+#pragma unroll
+  for (int u = 0; u < kSlabItemSlots; ++u) {
+    const int it = threadIdx.x + u * 1024;
+    if (it < a.nitems) {
+#pragma unroll
+      for (int q = 0; q < kItemEdges; ++q) {
+        const int e = a.itemE[(size_t)it * kItemEdges + q];
+        if (e >= 0) a.part[(size_t)e * a.ntile + g] = pad ? 0.0 : acc[u][q];
+      }
+    }
   }
 }
 
@@ -1967,10 +2086,20 @@ static void launch_edge_p(Problem *P, int init, int nbp) {
     }
     return;
   }
-  if (P->eslab) {
+  if (P->eslab && P->eslab_items) {
+    const Launch Ls{P->entile, 0, (int)P->n_items};
+    const EdgeArgs ea = edge_args(P, Ls, init, nbp);
+    const size_t lds = (size_t)P->n * (P->edge_f + kSlabPad) * sizeof(typename Traits<PREC>::TG);
+    switch (P->edge_f) {
+      case 4: klaunch(k_edge_slab_items<PREC, 4>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
+      case 8: klaunch(k_edge_slab_items<PREC, 8>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
+      case 16: klaunch(k_edge_slab_items<PREC, 16>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
+      default: klaunch(k_edge_slab_items<PREC, 32>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
+    }
+  } else if (P->eslab) {
     const Launch Ls{P->entile, 0, 0};
     const EdgeArgs ea = edge_args(P, Ls, init, nbp);
-    const size_t lds = (size_t)P->n * P->edge_f * sizeof(typename Traits<PREC>::TG);
+    const size_t lds = (size_t)P->n * (P->edge_f + kSlabPad) * sizeof(typename Traits<PREC>::TG);
     switch (P->edge_f) {
       case 4: klaunch(k_edge_slab<PREC, 4>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
       case 8: klaunch(k_edge_slab<PREC, 8>, dim3(P->entile), dim3(1024), lds, P->stream, P->pev[2], nullptr, ea, P->eslab_tpg, P->eslab_ntf); break;
@@ -2000,10 +2129,10 @@ static void set_slab_attr() {
   (void)hipFuncSetAttribute((const void *)k_edge_slab<PREC, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
   (void)hipFuncSetAttribute((const void *)k_edge_slab<PREC, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
   (void)hipFuncSetAttribute((const void *)k_edge_slab<PREC, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
-  (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
-  (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
-  (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
-  (void)hipFuncSetAttribute((const void *)k_point_slab<PREC, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_edge_slab_items<PREC, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_edge_slab_items<PREC, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_edge_slab_items<PREC, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
+  (void)hipFuncSetAttribute((const void *)k_edge_slab_items<PREC, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSlabBytes);
 }
 
 // Waves per block of the point sweep's launch.
@@ -2354,6 +2483,10 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
       }
     }
     P->n_items = (int64_t)iI.size();
+    if (P->eslab) {
+      const char *es = getenv("CCMI_EDGE_SLAB_ITEMS");
+      P->eslab_items = P->n_items <= (int64_t)kSlabItemSlots * 1024 && !(es && atoi(es) == 0);
+    }
     CC_TRY(dmalloc((void **)&P->itemI, iI.size() * 4));
     CC_TRY(dmalloc((void **)&P->itemJ, iJ.size() * 4));
     CC_TRY(dmalloc((void **)&P->itemE, iE.size() * 4));

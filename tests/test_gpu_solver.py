@@ -284,11 +284,13 @@ def test_point_sweep_prefetch(cc):
     assert rel_max(A, st.A) < 1e-11
 
 
-@pytest.mark.parametrize("edge_slab", ["0", "1"])
-def test_wide_rows_edge_variants(cc, edge_slab, monkeypatch):
+@pytest.mark.parametrize("edge_slab,slab_items", [("0", "1"), ("1", "0"), ("1", "1")])
+def test_wide_rows_edge_variants(cc, edge_slab, slab_items, monkeypatch):
     """Wide rows: the per-tile edge partials (CCMI_EDGE_SLAB=0) and the LDS
-    slab edge sweep agree with the oracle's trajectory."""
+    slab edge sweep, by single edges (CCMI_EDGE_SLAB_ITEMS=0) or by work
+    items of edges sharing a lower end, agree with the oracle's trajectory."""
     monkeypatch.setenv("CCMI_EDGE_SLAB", edge_slab)
+    monkeypatch.setenv("CCMI_EDGE_SLAB_ITEMS", slab_items)
     X, M, E, w, _ = reduced_expression(n=60, p=1100)
     st, _ = oracle_jacobi(X, M, E, w).solve(20.0, mm.Opts(tol=0, max_iter=40, proj="jacobi:1"))
     with _gpu(cc, X, M, E, w, "f64") as g:
@@ -296,6 +298,21 @@ def test_wide_rows_edge_variants(cc, edge_slab, monkeypatch):
         U, A, s = (t.cpu().numpy() for t in g.get_state())
     assert rel_max(U, st.U) < 1e-11
     assert np.abs(s - st.s).max() < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["f32", "mixed"])
+def test_slab_edge_items_are_bitwise_the_edge_order(cc, precision, monkeypatch):
+    """The slab edge sweep by work items adds each edge's features in the
+    same order as the sweep by single edges: identical iterates."""
+    X, M, E, w, _ = reduced_expression(n=60, p=1100)
+    out = []
+    for items in ("0", "1"):
+        monkeypatch.setenv("CCMI_EDGE_SLAB_ITEMS", items)
+        with _gpu(cc, X, M, E, w, precision) as g:
+            g.solve(20.0, tol=0.0, max_iter=30)
+            out.append([t.cpu().numpy() for t in g.get_state()])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
 
 
 # ------------------------------------------------------- sampled kernel timing
