@@ -83,18 +83,29 @@ def algorithmic_bytes(n, p, E, has_mask):
     return point, iteration, k1
 
 
-def implementation_bytes(n, p, E, precision, has_mask):
-    """Bytes one point-sweep launch of this implementation moves: with
-    missing data it reads U (else U_m follows from X and A'), and the mixed
+def implementation_bytes(n, p, E, precision, has_mask, missing=0):
+    """Bytes one point-sweep launch of this implementation moves.  The mixed
     precision keeps U and A in FP64 beside an FP32 gather copy of A (its own
-    row read, the new one written).  Same per-edge bytes as the algorithmic
-    count.  Returns (bytes per launch, bytes per point-feature)."""
+    row read, the new one written).  Without missing data U_m follows from
+    X and A', so U is neither read nor written (it is rebuilt once at the
+    end of a solve).  With missing data and one work item per wave (the
+    expression workload) U is read and written in full; where waves take
+    several items it is read and written only at the `missing` entries, in
+    a side array.  Same per-edge bytes as the algorithmic count.  Returns
+    (bytes per launch, bytes per point-feature outside the side array)."""
     sx = 8 if precision == "f64" else 4
     ss = 4 if precision == "f32" else 8
-    per_pf = sx + (1 + ss if has_mask else 0) + ss + ss + ss
+    per_pf = sx + ss + ss                   # X, A' read, A written
     if precision == "mixed":
-        per_pf += 4 + 4
-    return n * p * per_pf + 24 * E, per_pf
+        per_pf += 4 + 4                     # own gather row read, new one written
+    side = 0
+    if has_mask:
+        per_pf += 1                         # mask
+        if missing:
+            side = 2 * ss * missing
+        else:
+            per_pf += 2 * ss                # U read and written
+    return n * p * per_pf + side + 24 * E, per_pf
 
 
 TRAFFIC_PROFILES = {
@@ -644,7 +655,7 @@ def run_workload(cc, name, precision, steps, warmup, max_iter, sample_every, log
             "bytes_per_point_feature": k1,
             "bytes_rule": f"{k1} B per point-feature (FP32 state: X, "
                           + ("mask, " if has_mask else "") + "U read and write, A' read, A write) + 24 B per edge",
-            "precision_overhead_bytes": impl_point - alg_point,
+            "implementation_bytes_per_launch": impl_point,
             "implementation_bytes_per_point_feature": impl_pf,
             "iteration": {"bytes": alg_iter, "bytes_rule": f"{k1 + 8} B per point-feature + 60 B per edge",
                           "achieved": it_achieved, "frac": it_achieved / HBM_PEAK_GBS},

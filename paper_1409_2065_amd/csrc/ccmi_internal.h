@@ -48,6 +48,11 @@ struct DevScalars {
   double F_last, d_last, rel_last;
   int path_k;     // batched: index of the gamma in progress
   int finished;   // batched: the whole gamma path is done
+  // the last point sweep that ran: its iteration index, the buffer of its
+  // A' and its U-update weight theta (U is rebuilt from these when the
+  // sweep does not store it)
+  int m_run, pa_run;
+  double theta_run;
 };
 
 // Batched solves: what the device needs to move an instance along its gamma
@@ -85,6 +90,14 @@ struct Problem {
   int64_t n_items = 0;       // edge work items (up to kItemEdges edges each)
   bool eslab = false;        // wide rows, small n: LDS-slab edge sweep
   bool eslab_items = false;  // the slab sweep takes edges in work items
+  // U stored lazily (single solves with one projection sweep): the point
+  // sweep keeps U only at missing entries, in a side array (Umiss, FP state
+  // type) indexed from per-item offsets (moff, built for tile width vec)
+  bool lazy_u = false;
+  void *Umiss = nullptr;
+  int32_t *moff = nullptr;
+  int64_t n_miss = 0;
+  int moff_vec = 0;
   int eslab_tpg = 1;         // feature tiles per block of the slab edge sweep
   int eslab_ntf = 1;         // feature tiles of width edge_f
   int edge_f = 0;            // LDS tile width of the slab edge sweep

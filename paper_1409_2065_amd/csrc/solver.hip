@@ -345,6 +345,11 @@ struct PointArgs {
   // several projection sweeps per MM iteration (k_point_rhs only)
   double *H;              // h_i = sum_j s_ij (a'_i - a'_j), FP64
   void *T0;               // gather copy of the first sweep's increment A - A'
+  // U stored lazily (k_point only): U is written only at missing entries,
+  // into Umiss at offsets moff[item] + the entry's rank within its item
+  int lazy;
+  void *Umiss;
+  const int32_t *moff;
 };
 
 // Per-edge bookkeeping shared by the fused edge kernel and the reduction
@@ -488,6 +493,25 @@ __device__ inline void next_gamma(DevScalars &h, const BatchInst &bi, const Blk 
 // iteration; block 0 stores the scalars of the iteration about to run (or
 // the final ones) in the other slot.  Blocks of NW waves; red:
 // (NW + 1) * kIterSums.
+// The U update of an MM iteration (Missing Data: y is x on observed entries
+// and the previous u elsewhere): one fused multiply-add, so that every
+// kernel that forms or rebuilds u rounds it the same way.
+__device__ __forceinline__ double mm_u(double ap, double theta, double y) {
+  return fma(theta, y - ap, ap);
+}
+
+// Rank of each missing entry of a work item in the side array of a lazily
+// stored U: entries are numbered by feature slot v, then by lane.  mb[v]
+// holds the ballot of lanes whose slot v is missing.
+template <int VEC>
+__device__ __forceinline__ void miss_ballots(uint32_t mr, bool active, uint64_t (&mb)[VEC]) {
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) mb[v] = __ballot(active && ((mr >> (8 * v)) & 0xffu) == 0u);
+}
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 template <int NW, bool BATCH = false>
 __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, const Blk blk) {
   double v[kIterSums];
@@ -516,6 +540,11 @@ __device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, co
     }
   }
   h.pending = h.done ? 0 : 1;
+  if (!h.done) {
+    h.m_run = h.m;
+    h.pa_run = h.pa;
+    h.theta_run = (h.m > 0) ? h.d_prev / (h.d_prev + h.rho) : 0.0;
+  }
   if (writer) *a.sout = h;
   return h;
 }
@@ -548,6 +577,13 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   // Without a mask the U row is read only in the first iteration of a solve
   // (afterwards U_m depends on X and A_{m-1} alone).
   const int first = it0 + wave;
+  // Lazily stored U: the sweep reads and writes U only at missing entries
+  // (Umiss), except in a solve's first iteration, which reads the U rows
+  bool lazy = false;
+  if constexpr (!BATCH && !JAC) lazy = a.lazy != 0;
+  const bool lzm = lazy && a.M != nullptr;
+  TS *Umiss = reinterpret_cast<TS *>(a.Umiss);
+  int mo0 = 0;  // the item's first rank in Umiss
   uint32_t mr0 = 0xffffffffu;
   int jl0 = -1;
   double ql0 = 0.0;
@@ -564,6 +600,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     const size_t rowc = (size_t)i * a.ld + (f0 < a.ld ? f0 : 0);
     mr0 = 0xffffffffu;
     if (a.M) mr0 = RawMask<VEC>::load(a.M + rowc);
+    if (lzm) mo0 = a.moff[item];
     jl0 = -1;
     ql0 = 0.0;
     if (lane < a.ell_s) {
@@ -579,15 +616,15 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     if constexpr (PF && VEC == 4) NtIO<TX, 4>::load(X + rowc, x0);
     else RawIO<TX, VEC>::load(X + rowc, x0);
   };
-  if (first < it1) preload(first, a.M != nullptr);
+  if (first < it1) preload(first, a.M != nullptr && !lazy);
 
   const DevScalars hs = begin_iteration<NW, BATCH>(a, red, blk);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
-  const bool needU = a.M != nullptr || m == 0;
-  if (!a.M && m == 0 && first < it1) u_row(first, up0);
+  const bool needU = (a.M != nullptr && !lazy) || m == 0;
+  if ((!a.M || lazy) && m == 0 && first < it1) u_row(first, up0);
   const double rho = hs.rho, dprev = hs.d_prev;
-  const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
+  const double theta = hs.theta_run;
   // stop-test window: U snapshots at m = 0, K, 2K, ...; A snapshots at
   // m = K-1, 2K-1, ... (the start-of-solve A' seeds the first A window)
   const int K = a.K;
@@ -631,6 +668,26 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
       }
       if (needU) u_row(item, upr);
       RawIO<TX, VEC>::load(X + rowc, xr);
+    }
+    // missing entries of a lazily stored U: u_{m-1} from the side array
+    // (the ballots are formed again for the stores: fewer live registers)
+    int mbase = mo0;
+    if (lzm) {
+      if (!PF && item != first) mbase = a.moff[item];
+      if (m > 0) {
+        uint64_t mb[VEC];
+        miss_ballots<VEC>(mr, active, mb);
+        // unconditional loads, so that the wait counts stay exact: observed
+        // entries read entry 0 into a u they do not use after the first
+        // iteration
+        int off = mbase;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const bool miss = (mb[v] >> lane) & 1ull;
+          upr[v] = Umiss[miss ? off + lanes_below(mb[v]) : 0];
+          off += __popcll(mb[v]);
+        }
+      }
     }
     TG gr[VEC];
     TS apr[VEC];
@@ -743,7 +800,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
         double uu;
         if (m > 0) {
           const double y = mk[v] ? x[v] : up[v];
-          uu = ap[v] + theta * (y - ap[v]);
+          uu = mm_u(ap[v], theta, y);
         } else {
           uu = up[v];
         }
@@ -774,12 +831,24 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
         // U and, with an FP32 gather copy, A are streaming rows; where A is
         // itself what the next sweep gathers (no copy) it keeps ordinary
         // stores, so that it stays cached for those gathers
-        NtIO<TS, 4>::store(U + row, u);
+        if (!lazy) NtIO<TS, 4>::store(U + row, u);
         if constexpr (Traits<PREC>::mirror) NtIO<TS, 4>::store(An + row, an);
         else VecIO<VEC>::store(An + row, an);
       } else {
-        VecIO<VEC>::store(U + row, u);
+        if (!lazy) VecIO<VEC>::store(U + row, u);
         VecIO<VEC>::store(An + row, an);
+      }
+      if (lzm) {
+        // inside the active lanes: the ballots see exactly the lanes whose
+        // entries can be missing
+        uint64_t mb[VEC];
+        miss_ballots<VEC>(mr, true, mb);
+        int off = mbase;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          if ((mb[v] >> lane) & 1ull) Umiss[off + lanes_below(mb[v])] = (TS)u[v];
+          off += __popcll(mb[v]);
+        }
       }
       if constexpr (!JAC && Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, gn);
       if (winU) {
@@ -812,9 +881,10 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
 }
 
 // PF: prefetch each next item (for waves with several items).  NW waves
-// per block.
+// per block.  The FP32 and mixed sweeps are held to 128 VGPRs (4 waves per
+// SIMD); the FP64 one needs more and runs at 2.
 template <int PREC, int VEC, bool PF, int NW = kPointWaves>
-__global__ __launch_bounds__(kWave * NW) void k_point(PointArgs a) {
+__global__ __launch_bounds__(kWave * NW) __attribute__((amdgpu_waves_per_eu(PREC == kF64 ? 1 : 4))) void k_point(PointArgs a) {
   point_sweep<PREC, VEC, PF, false, false, NW>(a, hw_blk());
 }
 
@@ -822,6 +892,55 @@ __global__ __launch_bounds__(kWave * NW) void k_point(PointArgs a) {
 template <int PREC, int VEC, bool PF>
 __global__ __launch_bounds__(kPointBlock) void k_point_rhs(PointArgs a) {
   point_sweep<PREC, VEC, PF, false, true>(a, hw_blk());
+}
+
+// End of a solve whose point sweeps stored U lazily: rebuild U as the last
+// sweep that ran formed it.  Observed entries (all, without a mask) are
+// formed again from that sweep's A' and theta with the same arithmetic;
+// missing ones come from the side array.  A wave per (point, tile) item.
+template <int PREC, int VEC>
+__global__ __launch_bounds__(kPointBlock) void k_u_finish(PointArgs a) {
+  using TS = typename Traits<PREC>::TS;
+  using TX = typename Traits<PREC>::TX;
+  const DevScalars h = *a.sin;
+  if (h.m_run == 0) return;  // a first iteration leaves U as it was
+  const int lane = threadIdx.x % kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int W = kWave * VEC;
+  const TS *Ap = reinterpret_cast<const TS *>(h.pa_run == 0 ? a.A0 : a.A1);
+  const TX *X = reinterpret_cast<const TX *>(a.X);
+  TS *U = reinterpret_cast<TS *>(a.U);
+  const TS *Umiss = reinterpret_cast<const TS *>(a.Umiss);
+  const double theta = h.theta_run;
+  for (int item = blockIdx.x * kPointWaves + wave; item < a.nitems; item += gridDim.x * kPointWaves) {
+    const int t = item / a.n, i = item - t * a.n;
+    const int f0 = t * W + lane * VEC;
+    const bool active = f0 < a.ld;
+    const size_t rowc = (size_t)i * a.ld + (active ? f0 : 0);
+    uint32_t mr = 0xffffffffu;
+    if (a.M) mr = RawMask<VEC>::load(a.M + rowc);
+    TS apr[VEC];
+    TX xr[VEC];
+    RawIO<TS, VEC>::load(Ap + rowc, apr);
+    RawIO<TX, VEC>::load(X + rowc, xr);
+    uint64_t mb[VEC];
+    int off = 0;
+    if (a.M) {
+      off = a.moff[item];
+      miss_ballots<VEC>(mr, active, mb);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) mb[v] = 0ull;
+    }
+    double u[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      if ((mb[v] >> lane) & 1ull) u[v] = (double)Umiss[off + lanes_below(mb[v])];
+      else u[v] = round_to<TS>(mm_u((double)apr[v], theta, (double)xr[v]));
+      off += __popcll(mb[v]);
+    }
+    if (active) VecIO<VEC>::store(U + (size_t)i * a.ld + f0, u);
+  }
 }
 
 // Batched: block q works for instance tab[q].x as its local block tab[q].y.
@@ -856,7 +975,7 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
   const double rho = hs.rho, dprev = hs.d_prev;
-  const double theta = (m > 0) ? dprev / (dprev + rho) : 0.0;
+  const double theta = hs.theta_run;
   const int K = a.K;
   const bool snapU0 = (m == 0), winU = (m > 0) && (m % K == 0);
   const bool initA = (m == 0) && (K > 1), winA = (m % K) == (K - 1);
@@ -943,7 +1062,7 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
             double uu;
             if (m > 0) {
               const double y = mk[v] ? x[v] : up[v];
-              uu = ap[v] + theta * (y - ap[v]);
+              uu = mm_u(ap[v], theta, y);
             } else {
               uu = up[v];
             }
@@ -1954,7 +2073,7 @@ static PointArgs point_args(Problem *P, const Launch &Lp) {
                    P->X, P->M, P->U, P->A[0], P->A[1], P->G[0], P->G[1], P->Usnap, P->Asnap,
                    P->ell_s, P->degE, P->colE, P->eidE, P->qE, P->s, P->cur_K, Lp.blocks,
                    P->psum, P->esum, P->nbe, P->trace, P->sc + P->slot, P->sc + (P->slot ^ 1), nullptr,
-                   P->H, P->T[0]};
+                   P->H, P->T[0], P->lazy_u ? 1 : 0, P->Umiss, P->moff};
 }
 
 // Projection sweeps 2..K after k_point_rhs (scalars: the slot the point
@@ -2172,6 +2291,23 @@ static void launch_point_p(Problem *P, const Launch &Lp) {
 
 // One launch pair: the point sweep (which first finishes the pending
 // iteration) and the edge stage.  Advances the host's scalar slot.
+// U of a lazily stored solve (after its last iteration).
+template <int PREC>
+static void launch_u_finish_p(Problem *P) {
+  const Launch L = sweep_grid(P->n * P->ntile, kPointWaves);
+  const PointArgs a = point_args(P, L);
+  switch (P->vec) {
+    case 1: klaunch(k_u_finish<PREC, 1>, dim3(L.blocks), dim3(kPointBlock), 0, P->stream, nullptr, nullptr, a); break;
+    case 2: klaunch(k_u_finish<PREC, 2>, dim3(L.blocks), dim3(kPointBlock), 0, P->stream, nullptr, nullptr, a); break;
+    default: klaunch(k_u_finish<PREC, 4>, dim3(L.blocks), dim3(kPointBlock), 0, P->stream, nullptr, nullptr, a); break;
+  }
+}
+static void launch_u_finish(Problem *P) {
+  if (P->precision == kF32) launch_u_finish_p<kF32>(P);
+  else if (P->precision == kF64) launch_u_finish_p<kF64>(P);
+  else launch_u_finish_p<kMixed>(P);
+}
+
 static void launch_iteration(Problem *P) {
   hipEvent_t *ev = prof_slot(P);
   for (int q = 0; q < 4; ++q) P->pev[q] = ev ? ev[q] : nullptr;
@@ -2239,7 +2375,7 @@ void problem_free(Problem *P) {
                   P->itemI, P->itemJ, P->itemE,
                   P->ei, P->ej, P->w, P->s, P->nb[0], P->nb[1], P->qe, P->qE, P->epos, P->degE, P->colE,
                   P->eidE, P->part, P->psum,
-                  P->esum, P->trace, P->sc, P->ncl_dev, P->H, P->T[0], P->T[1]};
+                  P->esum, P->trace, P->sc, P->ncl_dev, P->H, P->T[0], P->T[1], P->Umiss, P->moff};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (Traits<kMixed>::mirror && P->precision == kMixed) {
@@ -2645,6 +2781,39 @@ static void solve_constants(const Problem *P, double gamma, const cc_solve_opts 
   *thr = o.tol > 0 ? o.tol * eta : 0.0;
 }
 
+// Offsets of the missing entries of each (point, tile) work item at the
+// current tile width, in item order, and the side array they index.
+static cc_status build_miss_index(Problem *P) {
+  if (P->moff) (void)hipFree(P->moff);
+  if (P->Umiss) (void)hipFree(P->Umiss);
+  P->moff = nullptr;
+  P->Umiss = nullptr;
+  P->n_miss = 0;
+  const int64_t n = P->n, ld = P->ld, W = (int64_t)kWave * P->vec, nt = P->ntile;
+  std::vector<uint8_t> m((size_t)(n * ld));
+  CC_HIP(hipMemcpyAsync(m.data(), P->M, m.size(), hipMemcpyDeviceToHost, P->stream));
+  CC_HIP(hipStreamSynchronize(P->stream));
+  std::vector<int32_t> off((size_t)(n * nt + 1));
+  int64_t tot = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t f1 = std::min(ld, (t + 1) * W);
+    for (int64_t i = 0; i < n; ++i) {
+      off[(size_t)(t * n + i)] = (int32_t)tot;
+      const uint8_t *r = m.data() + i * ld;
+      for (int64_t f = t * W; f < f1; ++f) tot += r[f] == 0;
+      if (tot > INT32_MAX) { set_error("too many missing entries for the lazy U index"); return CC_ERR_INVALID_ARG; }
+    }
+  }
+  off[(size_t)(n * nt)] = (int32_t)tot;
+  CC_TRY(dmalloc((void **)&P->moff, off.size() * 4));
+  CC_TRY(dmalloc(&P->Umiss, (size_t)std::max<int64_t>(tot, 1) * ts_size(P->precision)));
+  CC_HIP(hipMemcpyAsync(P->moff, off.data(), off.size() * 4, hipMemcpyHostToDevice, P->stream));
+  CC_HIP(hipStreamSynchronize(P->stream));  // the host vector goes out of scope
+  P->n_miss = tot;
+  P->moff_vec = P->vec;
+  return CC_OK;
+}
+
 cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info *info) {
   if (!(gamma >= 0.0) || !std::isfinite(gamma)) { set_error("gamma must be finite and >= 0"); return CC_ERR_INVALID_ARG; }
   if (o.max_iter < 1) { set_error("max_iter must be >= 1"); return CC_ERR_INVALID_ARG; }
@@ -2666,6 +2835,18 @@ cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info 
     CC_TRY(dmalloc(&P->T[1], nl * tg_size(P->precision)));
   }
   P->psweeps = o.proj_sweeps;
+  // U stored lazily by the wave point sweep with one projection sweep.
+  // With missing data the sweep then reads and writes a side array at
+  // dependent offsets, which pays only where waves take several items (the
+  // sweep streams bytes); waves with one item wait on latency, not bytes.
+  // CCMI_LAZY_U: 0 never, 2 always, else that rule.
+  const char *lz = getenv("CCMI_LAZY_U");
+  const int lzmode = lz ? atoi(lz) : 1;
+  P->lazy_u = P->psweeps == 1 && P->slab_f == 0 && lzmode != 0 &&
+              (!P->M || lzmode == 2 || point_grid(P).chunk > point_waves(P));
+  if (P->lazy_u && P->M && (!P->moff || P->moff_vec != P->vec)) {
+    if (build_miss_index(P) != CC_OK) P->lazy_u = false;  // store U every iteration
+  }
   const auto t0 = std::chrono::steady_clock::now();
   if (!o.warm_start || !P->state_valid) CC_TRY(reset_state(P));
   double rho, eps, thr;
@@ -2698,6 +2879,10 @@ cc_status solve(Problem *P, double gamma, const cc_solve_opts &o, cc_solve_info 
       if (P->prof_used) harvest_profile(P);
       if (P->flag_host[0]) break;
     }
+  }
+  if (P->lazy_u) {
+    launch_u_finish(P);
+    CC_HIP(hipGetLastError());
   }
   CC_TRY(read_scalars(P));
   const DevScalars &h = *P->sc_host;
@@ -2976,6 +3161,7 @@ static cc_status build_launch_set(LaunchSet &L, const std::vector<Problem *> &pr
       P->slot = par;
       PointArgs x = point_args(P, Lp);
       x.bi = bis[b];
+      x.lazy = 0;  // batched sweeps store U every iteration
       pa[par].push_back(x);
       P->slot = par ^ 1;
       ea[par].push_back(edge_args(P, Li, 0, Lp.blocks));

@@ -30,16 +30,23 @@ def test_algorithmic_bytes(mask, k1):
     assert it == 2000 * 500 * (k1 + 8) + 60 * 22965
 
 
-# what this implementation moves: without a mask the point sweep reads U only
-# in a solve's first iteration; the mixed precision keeps FP64 U and A and
-# an FP32 gather copy of A
+# what this implementation moves: the mixed precision keeps FP64 U and A and
+# an FP32 gather copy of A; without a mask U is neither read nor written (it
+# follows from X and A'); with a mask and one item per wave U is read and
+# written in full, with several items per wave only at the missing entries
 @pytest.mark.parametrize("prec,mask,expect", [("mixed", True, 45), ("f32", True, 21),
-                                              ("f64", True, 41), ("mixed", False, 36),
-                                              ("f32", False, 16)])
+                                              ("f64", True, 41), ("mixed", False, 28),
+                                              ("f32", False, 12), ("f64", False, 24)])
 def test_implementation_bytes(prec, mask, expect):
     b, per_pf = bench.implementation_bytes(2000, 500, 22965, prec, mask)
     assert per_pf == expect
     assert b == 2000 * 500 * expect + 24 * 22965
+
+
+def test_implementation_bytes_side_array():
+    b, per_pf = bench.implementation_bytes(2000, 500, 22965, "mixed", True, missing=50000)
+    assert per_pf == 29
+    assert b == 2000 * 500 * 29 + 16 * 50000 + 24 * 22965
 
 
 def test_host_cpu_description():
