@@ -655,6 +655,7 @@ def run_workload(cc, name, precision, steps, warmup, max_iter, sample_every, log
             "bytes_per_point_feature": k1,
             "bytes_rule": f"{k1} B per point-feature (FP32 state: X, "
                           + ("mask, " if has_mask else "") + "U read and write, A' read, A write) + 24 B per edge",
+            "precision_overhead_bytes": impl_point - alg_point,
             "implementation_bytes_per_launch": impl_point,
             "implementation_bytes_per_point_feature": impl_pf,
             "iteration": {"bytes": alg_iter, "bytes_rule": f"{k1 + 8} B per point-feature + 60 B per edge",
