@@ -85,17 +85,20 @@ def algorithmic_bytes(n, p, E, has_mask):
 
 def implementation_bytes(n, p, E, precision, has_mask, missing=0):
     """Bytes one point-sweep launch of this implementation moves.  The mixed
-    precision keeps U and A in FP64 beside an FP32 gather copy of A (its own
-    row read, the new one written).  Without missing data U_m follows from
-    X and A', so U is neither read nor written (it is rebuilt once at the
-    end of a solve).  With missing data and one work item per wave (the
-    expression workload) U is read and written in full; where waves take
-    several items it is read and written only at the `missing` entries, in
-    a side array.  Same per-edge bytes as the algorithmic count.  Returns
-    (bytes per launch, bytes per point-feature outside the side array)."""
+    precision keeps U in FP64 and A as hi + lo: hi is the FP32 gather copy
+    (its own row read, the new one written) and lo an FP32 low half, so A
+    costs 4 + 4 bytes per entry beyond the gather copy.  Without missing data
+    U_m follows from X and A', so U is neither read nor written (it is
+    rebuilt once at the end of a solve).  With missing data and one work
+    item per wave (the expression workload) U is read and written in full;
+    where waves take several items it is read and written only at the
+    `missing` entries, in a side array.  Same per-edge bytes as the
+    algorithmic count.  Returns (bytes per launch, bytes per point-feature
+    outside the side array)."""
     sx = 8 if precision == "f64" else 4
-    ss = 4 if precision == "f32" else 8
-    per_pf = sx + ss + ss                   # X, A' read, A written
+    ss = 4 if precision == "f32" else 8     # U
+    sa = 8 if precision == "f64" else 4     # the stored A array
+    per_pf = sx + sa + sa                   # X, A' read, A written
     if precision == "mixed":
         per_pf += 4 + 4                     # own gather row read, new one written
     side = 0

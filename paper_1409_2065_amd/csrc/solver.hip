@@ -53,17 +53,21 @@ namespace ccmi {
 
 // ------------------------------------------------------------------ traits
 template <int PREC> struct Traits;
+// TS: U and the stop-test snapshots; TG: the rows the pair sweeps gather;
+// TA: the stored A array.  The mixed precision stores A as hi + lo: hi is
+// the FP32 gather copy itself and lo (TA) the FP32 rounding of a - hi, 48
+// significant bits in all, so the sweeps move 8 bytes of A per entry.
 template <> struct Traits<kF32> {
-  using TS = float; using TG = float; using TX = float;
-  static constexpr bool mirror = false;
+  using TS = float; using TG = float; using TX = float; using TA = float;
+  static constexpr bool mirror = false, hilo = false;
 };
 template <> struct Traits<kMixed> {
-  using TS = double; using TG = float; using TX = float;
-  static constexpr bool mirror = true;
+  using TS = double; using TG = float; using TX = float; using TA = float;
+  static constexpr bool mirror = true, hilo = true;
 };
 template <> struct Traits<kF64> {
-  using TS = double; using TG = double; using TX = double;
-  static constexpr bool mirror = false;
+  using TS = double; using TG = double; using TX = double; using TA = double;
+  static constexpr bool mirror = false, hilo = false;
 };
 
 // ------------------------------------------------------ vector load/store
@@ -203,6 +207,29 @@ template <> struct RawIO<double, 1> {
 };
 
 template <typename T> __device__ inline double round_to(double v) { return (double)(T)v; }
+
+// A new entry of A as the state stores it: returns the stored value, with g
+// the gather copy's value and lo the stored low half (mixed precision; the
+// state is exactly g + lo and g is the nearest FP32 value to it).
+template <int PREC>
+__device__ __forceinline__ double state_round(double a, double &g, double &lo) {
+  if constexpr (Traits<PREC>::hilo) {
+    g = (double)(float)a;
+    lo = (double)(float)(a - g);
+    return g + lo;
+  } else {
+    const double r = round_to<typename Traits<PREC>::TS>(a);
+    g = round_to<typename Traits<PREC>::TG>(r);
+    lo = 0.0;
+    return r;
+  }
+}
+// A stored entry: g the gather copy's value, r the stored TA value.
+template <int PREC>
+__device__ __forceinline__ double state_value(double g, double r) {
+  if constexpr (Traits<PREC>::hilo) return g + r;
+  else return r;
+}
 
 __device__ inline double readlane_d(double v, int k) {
   long long bits = __double_as_longlong(v);
@@ -559,6 +586,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   using TS = typename Traits<PREC>::TS;
   using TG = typename Traits<PREC>::TG;
   using TX = typename Traits<PREC>::TX;
+  using TA = typename Traits<PREC>::TA;
   __shared__ double scratch[NW * kPointSums];
   __shared__ double red[(NW + 1) * kIterSums];
   const TX *X = reinterpret_cast<const TX *>(a.X);
@@ -632,8 +660,8 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
   const bool initA = (m == 0) && (K > 1), winA = (m % K) == (K - 1);
   TS *Us = reinterpret_cast<TS *>(a.Usnap);
   TS *As = reinterpret_cast<TS *>(a.Asnap);
-  const TS *Ap = reinterpret_cast<const TS *>(pa == 0 ? a.A0 : a.A1);
-  TS *An = reinterpret_cast<TS *>(pa == 0 ? a.A1 : a.A0);
+  const TA *Ap = reinterpret_cast<const TA *>(pa == 0 ? a.A0 : a.A1);
+  TA *An = reinterpret_cast<TA *>(pa == 0 ? a.A1 : a.A0);
   const TG *Gp = reinterpret_cast<const TG *>(pa == 0 ? a.G0 : a.G1);
   TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
   double ps[kPointSums] = {0, 0, 0, 0, 0, 0};
@@ -690,10 +718,10 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
       }
     }
     TG gr[VEC];
-    TS apr[VEC];
+    TA apr[VEC];
     RawIO<TG, VEC>::load(Gp + rowc, gr);
-    if constexpr (PF && VEC == 4) NtIO<TS, 4>::load(Ap + rowc, apr);
-    else RawIO<TS, VEC>::load(Ap + rowc, apr);
+    if constexpr (PF && VEC == 4) NtIO<TA, 4>::load(Ap + rowc, apr);
+    else RawIO<TA, VEC>::load(Ap + rowc, apr);
     if (PF && item + NW < it1) preload(item + NW, needU);
     double sumg[VEC], sumcg[VEC];
 #pragma unroll
@@ -789,12 +817,14 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
       bool mk[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
-        gi[v] = (double)gr[v]; ap[v] = (double)apr[v]; up[v] = (double)upr[v]; x[v] = (double)xr[v];
+        gi[v] = (double)gr[v];
+        ap[v] = state_value<PREC>(gi[v], (double)apr[v]);
+        up[v] = (double)upr[v]; x[v] = (double)xr[v];
         mk[v] = ((mr >> (8 * v)) & 0xffu) != 0u;
       }
       const double inv1d = 1.0 / (1.0 + (double)deg);
       const double S = (double)deg - C;
-      double u[VEC], an[VEC], gn[VEC], rr[VEC];
+      double u[VEC], an[VEC], al[VEC], gn[VEC], rr[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         double uu;
@@ -807,10 +837,9 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
         uu = round_to<TS>(uu);
         const double jac = sumcg[v] - C * gi[v];                 // sum_j c (a'_j - a'_i)
         const double h = S * gi[v] - (sumg[v] - sumcg[v]);       // sum_j s (a'_i - a'_j)
-        double anew = ap[v] + (uu - ap[v] + jac) * inv1d;
-        anew = round_to<TS>(anew);
-        const double g = round_to<TG>(anew);
-        u[v] = uu; an[v] = anew; gn[v] = g;
+        double g, lo;
+        const double anew = state_round<PREC>(ap[v] + (uu - ap[v] + jac) * inv1d, g, lo);
+        u[v] = uu; an[v] = anew; al[v] = lo; gn[v] = g;
         if constexpr (JAC) {
           rr[v] = h;
           gn[v] = round_to<TG>(anew - ap[v]);
@@ -824,7 +853,17 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
       }
       if constexpr (JAC) {
         VecIO<VEC>::store(U + row, u);
-        VecIO<VEC>::store(An + row, an);
+        if constexpr (Traits<PREC>::hilo) {
+          // the first sweep's A as hi + lo: hi into the gather copy, which
+          // the later sweeps update in place (they gather increments)
+          double hi[VEC];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) hi[v] = an[v] - al[v];
+          VecIO<VEC>::store(An + row, al);
+          VecIO<VEC>::store(Gn + row, hi);
+        } else {
+          VecIO<VEC>::store(An + row, an);
+        }
         VecIO<VEC>::store(a.H + row, rr);
         VecIO<VEC>::store(reinterpret_cast<TG *>(a.T0) + row, gn);
       } else if constexpr (PF && VEC == 4) {
@@ -832,11 +871,13 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
         // itself what the next sweep gathers (no copy) it keeps ordinary
         // stores, so that it stays cached for those gathers
         if (!lazy) NtIO<TS, 4>::store(U + row, u);
-        if constexpr (Traits<PREC>::mirror) NtIO<TS, 4>::store(An + row, an);
+        if constexpr (Traits<PREC>::hilo) NtIO<TA, 4>::store(An + row, al);
+        else if constexpr (Traits<PREC>::mirror) NtIO<TA, 4>::store(An + row, an);
         else VecIO<VEC>::store(An + row, an);
       } else {
         if (!lazy) VecIO<VEC>::store(U + row, u);
-        VecIO<VEC>::store(An + row, an);
+        if constexpr (Traits<PREC>::hilo) VecIO<VEC>::store(An + row, al);
+        else VecIO<VEC>::store(An + row, an);
       }
       if (lzm) {
         // inside the active lanes: the ballots see exactly the lanes whose
@@ -902,12 +943,15 @@ template <int PREC, int VEC>
 __global__ __launch_bounds__(kPointBlock) void k_u_finish(PointArgs a) {
   using TS = typename Traits<PREC>::TS;
   using TX = typename Traits<PREC>::TX;
+  using TA = typename Traits<PREC>::TA;
+  using TG = typename Traits<PREC>::TG;
   const DevScalars h = *a.sin;
   if (h.m_run == 0) return;  // a first iteration leaves U as it was
   const int lane = threadIdx.x % kWave;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int W = kWave * VEC;
-  const TS *Ap = reinterpret_cast<const TS *>(h.pa_run == 0 ? a.A0 : a.A1);
+  const TA *Ap = reinterpret_cast<const TA *>(h.pa_run == 0 ? a.A0 : a.A1);
+  const TG *Gp = reinterpret_cast<const TG *>(h.pa_run == 0 ? a.G0 : a.G1);
   const TX *X = reinterpret_cast<const TX *>(a.X);
   TS *U = reinterpret_cast<TS *>(a.U);
   const TS *Umiss = reinterpret_cast<const TS *>(a.Umiss);
@@ -919,9 +963,11 @@ __global__ __launch_bounds__(kPointBlock) void k_u_finish(PointArgs a) {
     const size_t rowc = (size_t)i * a.ld + (active ? f0 : 0);
     uint32_t mr = 0xffffffffu;
     if (a.M) mr = RawMask<VEC>::load(a.M + rowc);
-    TS apr[VEC];
+    TA apr[VEC];
+    TG gr[VEC];
     TX xr[VEC];
-    RawIO<TS, VEC>::load(Ap + rowc, apr);
+    RawIO<TA, VEC>::load(Ap + rowc, apr);
+    if constexpr (Traits<PREC>::hilo) RawIO<TG, VEC>::load(Gp + rowc, gr);
     RawIO<TX, VEC>::load(X + rowc, xr);
     uint64_t mb[VEC];
     int off = 0;
@@ -936,7 +982,10 @@ __global__ __launch_bounds__(kPointBlock) void k_u_finish(PointArgs a) {
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       if ((mb[v] >> lane) & 1ull) u[v] = (double)Umiss[off + lanes_below(mb[v])];
-      else u[v] = round_to<TS>(mm_u((double)apr[v], theta, (double)xr[v]));
+      else {
+        const double ap = Traits<PREC>::hilo ? state_value<PREC>((double)gr[v], (double)apr[v]) : (double)apr[v];
+        u[v] = round_to<TS>(mm_u(ap, theta, (double)xr[v]));
+      }
       off += __popcll(mb[v]);
     }
     if (active) VecIO<VEC>::store(U + (size_t)i * a.ld + f0, u);
@@ -981,8 +1030,9 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
   const bool initA = (m == 0) && (K > 1), winA = (m % K) == (K - 1);
   TS *Us = reinterpret_cast<TS *>(a.Usnap);
   TS *As = reinterpret_cast<TS *>(a.Asnap);
-  const TS *Ap = reinterpret_cast<const TS *>(pa == 0 ? a.A0 : a.A1);
-  TS *An = reinterpret_cast<TS *>(pa == 0 ? a.A1 : a.A0);
+  using TA = typename Traits<PREC>::TA;
+  const TA *Ap = reinterpret_cast<const TA *>(pa == 0 ? a.A0 : a.A1);
+  TA *An = reinterpret_cast<TA *>(pa == 0 ? a.A1 : a.A0);
   const TG *Gp = reinterpret_cast<const TG *>(pa == 0 ? a.G0 : a.G1);
   TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
   const TX *X = reinterpret_cast<const TX *>(a.X);
@@ -1054,8 +1104,11 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
           VecIO<4>::load(X + row, x);
           if (a.M) VecIO<4>::load_mask(a.M + row, mk);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) gi[v] = (double)slab[(size_t)i * F + 4 * c4 + v];
-          double u[4], an[4], gn[4];
+          for (int v = 0; v < 4; ++v) {
+            gi[v] = (double)slab[(size_t)i * F + 4 * c4 + v];
+            ap[v] = state_value<PREC>(gi[v], ap[v]);
+          }
+          double u[4], an[4], al[4], gn[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int f = 4 * c4 + v;
@@ -1069,10 +1122,9 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
             uu = round_to<TS>(uu);
             const double jac = sumcg[f] - C * gi[v];
             const double h = S * gi[v] - (sumg[f] - sumcg[f]);
-            double anew = ap[v] + (uu - ap[v] + jac) * inv1d;
-            anew = round_to<TS>(anew);
-            const double gq = round_to<TG>(anew);
-            u[v] = uu; an[v] = anew; gn[v] = gq;
+            double gq, lo;
+            const double anew = state_round<PREC>(ap[v] + (uu - ap[v] + jac) * inv1d, gq, lo);
+            u[v] = uu; an[v] = anew; al[v] = lo; gn[v] = gq;
             const double dua = uu - anew;
             ps[0] = fma(dua, dua, ps[0]);
             if (mk[v]) { const double r = x[v] - uu; ps[3] = fma(r, r, ps[3]); }
@@ -1080,7 +1132,8 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
             ps[5] = fma(h, gq, ps[5]);
           }
           VecIO<4>::store(U + row, u);
-          VecIO<4>::store(An + row, an);
+          if constexpr (Traits<PREC>::hilo) VecIO<4>::store(An + row, al);
+          else VecIO<4>::store(An + row, an);
           if (Traits<PREC>::mirror) VecIO<4>::store(Gn + row, gn);
           if (winU) {
             double us[4];
@@ -1161,9 +1214,12 @@ __global__ __launch_bounds__(kPointBlock) void k_jacobi(JacArgs a) {
   const int W = kWave * VEC;
   const TG *Di = reinterpret_cast<const TG *>(a.Din);
   TG *Do = reinterpret_cast<TG *>(a.Dout);
+  using TA = typename Traits<PREC>::TA;
+  constexpr bool hilo = Traits<PREC>::hilo;
   TG *Gn = reinterpret_cast<TG *>(pa == 0 ? a.G1 : a.G0);
-  TS *An = reinterpret_cast<TS *>(pa == 0 ? a.A1 : a.A0);
-  const TS *Ap = reinterpret_cast<const TS *>(pa == 0 ? a.A0 : a.A1);
+  const TG *Gp = reinterpret_cast<const TG *>(pa == 0 ? a.G0 : a.G1);
+  TA *An = reinterpret_cast<TA *>(pa == 0 ? a.A1 : a.A0);
+  const TA *Ap = reinterpret_cast<const TA *>(pa == 0 ? a.A0 : a.A1);
   const TS *U = reinterpret_cast<const TS *>(a.U);
   TS *As = reinterpret_cast<TS *>(a.Asnap);
   double ps[3] = {0.0, 0.0, 0.0};
@@ -1176,8 +1232,12 @@ __global__ __launch_bounds__(kPointBlock) void k_jacobi(JacArgs a) {
     const size_t row = (size_t)i * a.ld + f0;
     const size_t rowc = (size_t)i * a.ld + f0c;
     const size_t rs = (size_t)i * a.ell_s;
-    TS akr[VEC];
-    RawIO<TS, VEC>::load(An + rowc, akr);
+    // the state being swept: A (FP32 and FP64), or its low half with the
+    // high half in the gather copy (mixed)
+    TA akr[VEC];
+    TG akh[VEC];
+    RawIO<TA, VEC>::load(An + rowc, akr);
+    if constexpr (hilo) RawIO<TG, VEC>::load(Gn + rowc, akh);
     double hr[VEC];
     TS ur[VEC];
     if constexpr (LAST) {
@@ -1232,14 +1292,20 @@ __global__ __launch_bounds__(kPointBlock) void k_jacobi(JacArgs a) {
     }
     if (active) {
       const double inv1d = 1.0 / (1.0 + (double)deg);
-      double an[VEC], dn[VEC];
+      double an[VEC], al[VEC], ah[VEC], dn[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         const double inc = sum[v] * inv1d;
-        an[v] = round_to<TS>((double)akr[v] + inc);
-        dn[v] = round_to<TG>(LAST ? an[v] : inc);
+        const double ak = hilo ? state_value<PREC>((double)akh[v], (double)akr[v]) : (double)akr[v];
+        an[v] = state_round<PREC>(ak + inc, ah[v], al[v]);
+        dn[v] = LAST ? ah[v] : round_to<TG>(inc);
       }
-      VecIO<VEC>::store(An + row, an);
+      if constexpr (hilo) {
+        VecIO<VEC>::store(An + row, al);
+        if constexpr (!LAST) VecIO<VEC>::store(Gn + row, ah);
+      } else {
+        VecIO<VEC>::store(An + row, an);
+      }
       if constexpr (LAST) {
         if (Traits<PREC>::mirror) VecIO<VEC>::store(Gn + row, dn);
 #pragma unroll
@@ -1250,8 +1316,17 @@ __global__ __launch_bounds__(kPointBlock) void k_jacobi(JacArgs a) {
         }
         if (winA) {
           double prev[VEC];
-          if (m == 0) VecIO<VEC>::load(Ap + row, prev);
-          else VecIO<VEC>::load(As + row, prev);
+          if (m == 0) {
+            VecIO<VEC>::load(Ap + row, prev);
+            if constexpr (hilo) {
+              double gp[VEC];
+              VecIO<VEC>::load(Gp + row, gp);
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) prev[v] = state_value<PREC>(gp[v], prev[v]);
+            }
+          } else {
+            VecIO<VEC>::load(As + row, prev);
+          }
 #pragma unroll
           for (int v = 0; v < VEC; ++v) { const double da = an[v] - prev[v]; ps[1] = fma(da, da, ps[1]); }
           VecIO<VEC>::store(As + row, an);
@@ -1916,8 +1991,10 @@ __global__ void k_init_state(int n, int p, int ld, const TI *Xin, int64_t ldx,
   reinterpret_cast<TX *>(Xo)[idx] = (TX)(obs ? x : xt);
   if (Mo) Mo[idx] = obs ? 1 : 0;
   reinterpret_cast<TS *>(Uo)[idx] = (TS)xt;
-  reinterpret_cast<TS *>(A0)[idx] = (TS)xt;
-  if (Traits<PREC>::mirror) reinterpret_cast<TG *>(G0)[idx] = (TG)(TS)xt;
+  double g, lo;
+  const double a = state_round<PREC>(xt, g, lo);
+  reinterpret_cast<typename Traits<PREC>::TA *>(A0)[idx] = (typename Traits<PREC>::TA)(Traits<PREC>::hilo ? lo : a);
+  if (Traits<PREC>::mirror) reinterpret_cast<TG *>(G0)[idx] = (TG)g;
 }
 
 __global__ void k_fill(double *v, int64_t n, double val) {
@@ -1944,8 +2021,19 @@ __global__ void k_set_rows(int n, int p, int ld, const double *U, const double *
   double u = 0.0, a = 0.0;
   if (f < p) { u = U[(size_t)i * lds + f]; a = A[(size_t)i * lds + f]; }
   reinterpret_cast<TS *>(Uo)[idx] = (TS)u;
-  reinterpret_cast<TS *>(Ao)[idx] = (TS)a;
-  if (Traits<PREC>::mirror) reinterpret_cast<TG *>(Go)[idx] = (TG)(TS)a;
+  double g, lo;
+  const double as = state_round<PREC>(a, g, lo);
+  reinterpret_cast<typename Traits<PREC>::TA *>(Ao)[idx] = (typename Traits<PREC>::TA)(Traits<PREC>::hilo ? lo : as);
+  if (Traits<PREC>::mirror) reinterpret_cast<TG *>(Go)[idx] = (TG)g;
+}
+
+// A of the mixed precision as FP64: the gather copy plus the low half.
+__global__ void k_get_hilo(int n, int p, const float *G, const float *L, int ld, double *dst, int64_t ldo) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * p) return;
+  const int i = (int)(idx / p), f = (int)(idx % p);
+  const size_t k = (size_t)i * ld + f;
+  dst[(size_t)i * ldo + f] = (double)G[k] + (double)L[k];
 }
 
 __global__ void k_fused_flags(int E, const double *s, uint8_t *out) {
@@ -2019,6 +2107,7 @@ constexpr int64_t kSlabBytes = 128 * 1024;  // LDS budget of the slab point swee
 static size_t ts_size(int prec) { return prec == kF32 ? 4 : 8; }
 static size_t tx_size(int prec) { return prec == kF64 ? 8 : 4; }
 static size_t tg_size(int prec) { return prec == kF64 ? 8 : 4; }
+static size_t ta_size(int prec) { return prec == kF64 ? 8 : 4; }  // the stored A array
 
 struct Launch {
   int blocks, chunk, nitems;
@@ -2544,8 +2633,8 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   CC_TRY(dmalloc(&P->X, nl * tx_size(precision)));
   if (mask) CC_TRY(dmalloc((void **)&P->M, nl));
   CC_TRY(dmalloc(&P->U, nl * ts_size(precision)));
-  CC_TRY(dmalloc(&P->A[0], nl * ts_size(precision)));
-  CC_TRY(dmalloc(&P->A[1], nl * ts_size(precision)));
+  CC_TRY(dmalloc(&P->A[0], nl * ta_size(precision)));
+  CC_TRY(dmalloc(&P->A[1], nl * ta_size(precision)));
   CC_TRY(dmalloc(&P->Usnap, nl * ts_size(precision)));
   CC_TRY(dmalloc(&P->Asnap, nl * ts_size(precision)));
   if (precision == kMixed) {
@@ -2743,9 +2832,8 @@ cc_status reset_state(Problem *P) {
     hipLaunchKernelGGL((k_copy_rows<float, double>), dim3(b), dim3(256), 0, P->stream,
                        (int)P->n, (int)P->ld, (const float *)P->X, (int)P->ld, (double *)P->U,
                        (int64_t)P->ld);
-    hipLaunchKernelGGL((k_copy_rows<float, double>), dim3(b), dim3(256), 0, P->stream,
-                       (int)P->n, (int)P->ld, (const float *)P->X, (int)P->ld,
-                       (double *)P->A[0], (int64_t)P->ld);
+    // A = X-tilde as hi + lo: the entries are FP32 values, so lo = 0
+    CC_HIP(hipMemsetAsync(P->A[0], 0, nl * ta_size(P->precision), P->stream));
     CC_HIP(hipMemcpyAsync(P->G[0], P->X, nl * 4, hipMemcpyDeviceToDevice, P->stream));
   }
   if (P->E > 0) {
@@ -2995,7 +3083,10 @@ cc_status get_state(Problem *P, double *U, double *A, int64_t ld, double *s) {
     hipLaunchKernelGGL((k_copy_rows<float, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const float *)P->A[pa], (int)P->ld, A, ld);
   } else {
     hipLaunchKernelGGL((k_copy_rows<double, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const double *)P->U, (int)P->ld, U, ld);
-    hipLaunchKernelGGL((k_copy_rows<double, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const double *)P->A[pa], (int)P->ld, A, ld);
+    if (P->precision == kMixed)
+      hipLaunchKernelGGL(k_get_hilo, dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const float *)P->G[pa], (const float *)P->A[pa], (int)P->ld, A, ld);
+    else
+      hipLaunchKernelGGL((k_copy_rows<double, double>), dim3(b), dim3(256), 0, P->stream, (int)P->n, (int)P->p, (const double *)P->A[pa], (int)P->ld, A, ld);
   }
   if (P->E > 0) CC_HIP(hipMemcpyAsync(s, P->s, P->E * 8, hipMemcpyDeviceToDevice, P->stream));
   CC_HIP(hipGetLastError());
@@ -3595,9 +3686,9 @@ static double host_seconds() {
 static int64_t request_bytes(int64_t n, int64_t p, int32_t k, bool mask, int precision, int64_t n_gamma) {
   const int64_t ld = (p + 3) / 4 * 4;
   const int64_t ts = precision == kF32 ? 4 : 8, tx = precision == kF64 ? 8 : 4;
-  const int64_t tg = precision == kMixed ? 4 : 0;
+  const int64_t tg = precision == kMixed ? 4 : 0, ta = precision == kF64 ? 8 : 4;
   const int64_t E = n * k;
-  return n * ld * (tx + (mask ? 1 : 0) + 5 * ts + 2 * tg) + E * (128 + n_gamma) + n * 2 * k * 16 +
+  return n * ld * (tx + (mask ? 1 : 0) + 3 * ts + 2 * ta + 2 * tg) + E * (128 + n_gamma) + n * 2 * k * 16 +
          n_gamma * kInfoVals * 8 + (int64_t)kMaxBlocks * 64;
 }
 

@@ -30,12 +30,13 @@ def test_algorithmic_bytes(mask, k1):
     assert it == 2000 * 500 * (k1 + 8) + 60 * 22965
 
 
-# what this implementation moves: the mixed precision keeps FP64 U and A and
-# an FP32 gather copy of A; without a mask U is neither read nor written (it
-# follows from X and A'); with a mask and one item per wave U is read and
-# written in full, with several items per wave only at the missing entries
-@pytest.mark.parametrize("prec,mask,expect", [("mixed", True, 45), ("f32", True, 21),
-                                              ("f64", True, 41), ("mixed", False, 28),
+# what this implementation moves: the mixed precision keeps FP64 U and A as
+# hi + lo (the FP32 gather copy and an FP32 low half); without a mask U is
+# neither read nor written (it follows from X and A'); with a mask and one
+# item per wave U is read and written in full, with several items per wave
+# only at the missing entries
+@pytest.mark.parametrize("prec,mask,expect", [("mixed", True, 37), ("f32", True, 21),
+                                              ("f64", True, 41), ("mixed", False, 20),
                                               ("f32", False, 12), ("f64", False, 24)])
 def test_implementation_bytes(prec, mask, expect):
     b, per_pf = bench.implementation_bytes(2000, 500, 22965, prec, mask)
@@ -45,8 +46,8 @@ def test_implementation_bytes(prec, mask, expect):
 
 def test_implementation_bytes_side_array():
     b, per_pf = bench.implementation_bytes(2000, 500, 22965, "mixed", True, missing=50000)
-    assert per_pf == 29
-    assert b == 2000 * 500 * 29 + 16 * 50000 + 24 * 22965
+    assert per_pf == 21
+    assert b == 2000 * 500 * 21 + 16 * 50000 + 24 * 22965
 
 
 def test_host_cpu_description():
