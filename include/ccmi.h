@@ -64,8 +64,9 @@ enum { CC_DTYPE_F32 = 0, CC_DTYPE_F64 = 1 };
 
 /* Storage precision of the solver state.
  *   CC_PREC_F32   U, A and the pair sweep in FP32; reductions FP64.
- *   CC_PREC_MIXED U and A (point-level state) in FP64, an FP32 copy of A for
- *                 the pair sweep, which runs in FP32; reductions, d, the
+ *   CC_PREC_MIXED U in FP64; A as the FP32 copy of A that the pair sweep
+ *                 gathers (which runs in FP32) plus an FP32 low half, 48
+ *                 significant bits; the point arithmetic, reductions, d, the
  *                 objective, the convergence test and every fusion decision
  *                 in FP64.  Default.
  *   CC_PREC_F64   everything FP64. */
