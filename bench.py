@@ -785,7 +785,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "f64 point state, f32 pair gathers", "f32": "f32", "f64": "f64"}[args.precision],
+        "dtype": {"mixed": "f64 point arithmetic and U, A as f32 hi + f32 lo, f32 pair gathers", "f32": "f32", "f64": "f64"}[args.precision],
         "data": "synthetic",
         "config": head["config"],
         "roofline": head["roofline"],
