@@ -114,7 +114,8 @@ def test_batched_instances_match_oracle(cc):
     iteration count within one test window; the centres after each gamma
     (from the same instance solved alone, which the batch equals bitwise)
     and after the path agree within 1e-5.  Both sides stop at tol 1e-4 or
-    5000 MM iterations per gamma (the batched benchmark's settings)."""
+    5000 MM iterations per gamma (tighter than the benchmark's tol 1e-3 and
+    1000-iteration cap)."""
     from oracle import mm
     opts = dict(max_iter=5000, tol=1e-4)
     ids = [14, 3, 24, 31, 2]

@@ -157,7 +157,8 @@ def test_served_requests_match_oracle(cc):
     data and mask: every gamma the oracle's stopping test passes is also
     converged on the server, with the same labels; the centres after the
     path agree within 1e-5.  Both sides stop at tol 1e-4 or 5000 MM
-    iterations per gamma (the served benchmark's settings)."""
+    iterations per gamma (tighter than the benchmark's tol 1e-3 and
+    1000-iteration cap)."""
     from oracle import mm, weights
     specs = [(41, 60, 20, 3, 0.1), (42, 120, 30, 4, 0.1), (43, 90, 50, 3, 0.0)]
     gam = [1e-2, 1.0, 10.0, 100.0]
