@@ -2725,6 +2725,12 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
   P->nbe = edge_rows(P);
   // ELL copy of the neighbour lists for the point sweep
   const int64_t S = std::max<int64_t>(maxdeg, 1);
+  // the sweeps index ELL slots (n * S of them) in 32 bits: checked before
+  // any of the n * S host or device arrays exists
+  if (n * S > ((int64_t)1 << 31) - 1) {
+    set_error("neighbour lists too large: n * max degree = " + std::to_string(n * S) + " >= 2^31");
+    return CC_ERR_INVALID_ARG;
+  }
   P->ell_s = (int)S;
   // unused slots: column -1 (the wave sweep counts neighbours by it), edge 0
   std::vector<int32_t> hdegE(n), hcolE(n * S, -1), heidE(n * S, 0), hposE(2 * E);
@@ -2745,7 +2751,6 @@ cc_status problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X,
     const int64_t row = (e2 % 2 == 0) ? hi[e2 / 2] : hj[e2 / 2];
     hposE[e2] = (int32_t)ell_slot(row, k - rp[row]);
   }
-  if ((int64_t)n * S > ((int64_t)1 << 31) - 1) { set_error("neighbour lists too large"); return CC_ERR_INVALID_ARG; }
   CC_TRY(dmalloc((void **)&P->degE, n * 4));
   CC_TRY(dmalloc((void **)&P->colE, n * S * 4));
   CC_TRY(dmalloc((void **)&P->eidE, n * S * 4));
