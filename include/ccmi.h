@@ -162,7 +162,8 @@ int32_t cc_version(void);
  *   stream      hipStream_t for all work of this problem.
  * The inputs are copied; the function synchronises the stream before
  * returning, so the caller may free them afterwards.  Observed X must be
- * finite.  On success *out owns the device state until cc_problem_destroy. */
+ * finite.  out must not be NULL; on success *out owns the device state until
+ * cc_problem_destroy, on failure *out is NULL. */
 cc_status cc_problem_create(int64_t n, int64_t p, int32_t x_dtype,
                             const void *X, int64_t ldx, const uint8_t *mask,
                             int64_t ldm, int64_t n_edges, const int32_t *ei,

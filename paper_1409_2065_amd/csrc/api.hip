@@ -99,6 +99,8 @@ cc_status cc_problem_create(int64_t n, int64_t p, int32_t x_dtype, const void *X
                             const int32_t *ei, const int32_t *ej, const double *w,
                             int32_t precision, void *stream, cc_problem_t *out) {
   CC_GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return CC_ERR_INVALID_ARG; }
+  *out = nullptr;
   Problem *P = nullptr;
   cc_status s = problem_create(n, p, x_dtype, X, ldx, mask, ldm, n_edges, ei, ej, w, precision,
                                (hipStream_t)stream, &P);
@@ -205,8 +207,12 @@ cc_status cc_batch_create(int32_t n_inst, const cc_problem_t *problems, const in
                           const double *gammas, const cc_solve_opts *opts, int32_t autotune,
                           cc_batch_t *out) {
   CC_GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return CC_ERR_INVALID_ARG; }
+  *out = nullptr;
   if (!opts_ok(opts)) { set_error("opts->struct_size mismatch"); return CC_ERR_INVALID_ARG; }
   if (n_inst < 1 || !problems) { set_error("need n_inst >= 1 problems"); return CC_ERR_INVALID_ARG; }
+  for (int32_t b = 0; b < n_inst; ++b)
+    if (!problems[b]) { set_error("problem " + std::to_string(b) + " is NULL"); return CC_ERR_INVALID_ARG; }
   const cc_solve_opts o = resolve(opts);
   std::vector<Problem *> probs(n_inst);
   for (int32_t b = 0; b < n_inst; ++b) probs[b] = reinterpret_cast<Problem *>(problems[b]);
@@ -274,6 +280,8 @@ cc_status cc_batch_destroy(cc_batch_t batch) {
 cc_status cc_server_create(int32_t precision, const cc_solve_opts *opts, int64_t hbm_budget,
                            int32_t max_active, int32_t round_iters, void *stream, cc_server_t *out) {
   CC_GUARD_BEGIN
+  if (!out) { set_error("out is NULL"); return CC_ERR_INVALID_ARG; }
+  *out = nullptr;
   if (!opts_ok(opts)) { set_error("opts->struct_size mismatch"); return CC_ERR_INVALID_ARG; }
   Server *S = nullptr;
   cc_status s = server_create(precision, resolve(opts), hbm_budget, max_active, round_iters,
