@@ -539,22 +539,43 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// The edge stage's partial rows that a point sweep's block sums first: at
+// most two per thread (blocks of at least 256 threads, at most kEsumRows
+// rows), each 5 aligned 16-byte loads.  They are issued before the sweep's
+// other loads, so that the finish of the previous iteration waits for them
+// alone (loads retire in order); loads are unconditional (row 0 stands in
+// for a missing row and is not added) so that the wait counts stay exact.
+struct EsumLoad {
+  double2 t[2][kEsumStride / 2];
+};
+
+template <int NW>
+__device__ inline void esum_issue(const PointArgs &a, EsumLoad &L) {
+  static_assert(NW * kWave * 2 >= kEsumRows, "at most two partial rows per thread");
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int b = threadIdx.x + r * NW * kWave;
+    const double2 *row = reinterpret_cast<const double2 *>(a.esum + (size_t)(b < a.nrows ? b : 0) * kEsumStride);
+#pragma unroll
+    for (int k = 0; k < kEsumStride / 2; ++k) L.t[r][k] = row[k];
+  }
+}
+
 template <int NW, bool BATCH = false>
-__device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, const Blk blk) {
+__device__ inline DevScalars begin_iteration(const PointArgs &a, double *red, const Blk blk,
+                                             const EsumLoad &L) {
   double v[kIterSums];
 #pragma unroll
   for (int q = 0; q < kIterSums; ++q) v[q] = 0.0;
-  // issued before the scalars are known; unused when nothing is pending.
-  // A row is 5 aligned 16-byte loads.
-  for (int b = threadIdx.x; b < a.nrows; b += NW * kWave) {
-    const double2 *r = reinterpret_cast<const double2 *>(a.esum + (size_t)b * kEsumStride);
-    double2 t[kEsumStride / 2];
+  // unused when nothing is pending
 #pragma unroll
-    for (int k = 0; k < kEsumStride / 2; ++k) t[k] = r[k];
+  for (int r = 0; r < 2; ++r) {
+    if (threadIdx.x + r * NW * kWave < a.nrows) {
 #pragma unroll
-    for (int k = 0; k < kEsumStride / 2; ++k) {
-      v[2 * k] += t[k].x;
-      if (2 * k + 1 < kIterSums) v[2 * k + 1] += t[k].y;
+      for (int k = 0; k < kEsumStride / 2; ++k) {
+        v[2 * k] += L.t[r][k].x;
+        if (2 * k + 1 < kIterSums) v[2 * k + 1] += L.t[r][k].y;
+      }
     }
   }
   DevScalars h = *a.sin;
@@ -622,31 +643,58 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     const int f0 = t * W + lane * VEC;
     RawIO<TS, VEC>::load(U + (size_t)i * a.ld + (f0 < a.ld ? f0 : 0), u);
   };
-  auto preload = [&](int item, bool needU) {
+  // exact: every load is issued whatever the case (no mask: 4 bytes of the
+  // slot list stand in; U not needed: row 0, the same lines for every wave;
+  // a lane past the list: slot 0) and the values are selected afterwards.
+  // Without branches the compiler counts the loads in flight exactly, so
+  // the partial rows issued before the first item's loads are waited for
+  // alone.  The prefetches of later items keep their conditions, which
+  // skip loads that are not needed.
+  auto preload = [&](int item, bool needU, bool exact) {
     const int t = item / a.n, i = item - t * a.n;
     const int f0 = t * W + lane * VEC;
-    const size_t rowc = (size_t)i * a.ld + (f0 < a.ld ? f0 : 0);
-    mr0 = 0xffffffffu;
-    if (a.M) mr0 = RawMask<VEC>::load(a.M + rowc);
+    const int f0c = f0 < a.ld ? f0 : 0;
+    const size_t rowc = (size_t)i * a.ld + f0c;
     if (lzm) mo0 = a.moff[item];
-    jl0 = -1;
-    ql0 = 0.0;
-    if (lane < a.ell_s) {
-      jl0 = a.colE[i * a.ell_s + lane];
-      ql0 = a.qE[i * a.ell_s + lane];  // unused in the first iteration of a solve
-    }
-    if (needU) {
-      RawIO<TS, VEC>::load(U + rowc, up0);
-    } else {
+    if (exact) {
+      const uint8_t *Mp = a.M ? a.M + rowc : reinterpret_cast<const uint8_t *>(a.colE);
+      const uint32_t mr = RawMask<VEC>::load(Mp);
+      mr0 = a.M ? mr : 0xffffffffu;
+      const bool has_slot = lane < a.ell_s;
+      const int slot = i * a.ell_s + (has_slot ? lane : 0);
+      const int jl = a.colE[slot];
+      const double ql = a.qE[slot];  // unused in the first iteration of a solve
+      jl0 = has_slot ? jl : -1;
+      ql0 = has_slot ? ql : 0.0;
+      TS ur[VEC];
+      RawIO<TS, VEC>::load(U + (needU ? rowc : (size_t)f0c), ur);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) up0[v] = (TS)0;
+      for (int v = 0; v < VEC; ++v) up0[v] = needU ? ur[v] : (TS)0;
+    } else {
+      mr0 = 0xffffffffu;
+      if (a.M) mr0 = RawMask<VEC>::load(a.M + rowc);
+      jl0 = -1;
+      ql0 = 0.0;
+      if (lane < a.ell_s) {
+        jl0 = a.colE[i * a.ell_s + lane];
+        ql0 = a.qE[i * a.ell_s + lane];
+      }
+      if (needU) {
+        RawIO<TS, VEC>::load(U + rowc, up0);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) up0[v] = (TS)0;
+      }
     }
     if constexpr (PF && VEC == 4) NtIO<TX, 4>::load(X + rowc, x0);
     else RawIO<TX, VEC>::load(X + rowc, x0);
   };
-  if (first < it1) preload(first, a.M != nullptr && !lazy);
+  EsumLoad el;
+  esum_issue<NW>(a, el);
+  // waves without an item preload item 0 and never use it
+  preload(first < it1 ? first : 0, a.M != nullptr && !lazy, true);
 
-  const DevScalars hs = begin_iteration<NW, BATCH>(a, red, blk);
+  const DevScalars hs = begin_iteration<NW, BATCH>(a, red, blk, el);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
   const bool needU = (a.M != nullptr && !lazy) || m == 0;
@@ -722,7 +770,7 @@ __device__ __forceinline__ void point_sweep(const PointArgs &a, const Blk blk) {
     RawIO<TG, VEC>::load(Gp + rowc, gr);
     if constexpr (PF && VEC == 4) NtIO<TA, 4>::load(Ap + rowc, apr);
     else RawIO<TA, VEC>::load(Ap + rowc, apr);
-    if (PF && item + NW < it1) preload(item + NW, needU);
+    if (PF && item + NW < it1) preload(item + NW, needU, false);
     double sumg[VEC], sumcg[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) sumg[v] = sumcg[v] = 0.0;
@@ -1020,7 +1068,9 @@ __global__ __launch_bounds__(kBlock) void k_point_slab(PointArgs a) {
   __shared__ double scratch[kWavesPerBlock * kPointSums];
   __shared__ double red[(kWavesPerBlock + 1) * kIterSums];
   const Blk blk = hw_blk();
-  const DevScalars hs = begin_iteration<kWavesPerBlock>(a, red, blk);
+  EsumLoad el;
+  esum_issue<kWavesPerBlock>(a, el);
+  const DevScalars hs = begin_iteration<kWavesPerBlock>(a, red, blk, el);
   if (hs.done) return;
   const int m = hs.m, pa = hs.pa;
   const double rho = hs.rho, dprev = hs.d_prev;
