@@ -262,7 +262,10 @@ cc_status cc_export_state(cc_problem_t prob, void *buf, size_t bytes);
 cc_status cc_import_state(cc_problem_t prob, const void *buf, size_t bytes);
 cc_status cc_reset_state(cc_problem_t prob);
 /* Set the state from device arrays: U and A' (float64, n rows of ld) and s
- * (float64, n_edges, in input edge order, each in [0, 1]). */
+ * (float64, n_edges, in input edge order, each in [0, 1]).  The values are
+ * rounded to the precision's storage: FP32 (CC_PREC_F32), FP64 U and A' as
+ * an FP32 high half plus an FP32 low half, 48 significant bits
+ * (CC_PREC_MIXED), FP64 (CC_PREC_F64). */
 cc_status cc_set_state(cc_problem_t prob, const double *U, const double *A,
                        int64_t ld, const double *s);
 /* Read the state into device arrays of the same form. */
