@@ -21,7 +21,7 @@ constexpr int kMaxBlocks = 2048; // grid cap for the grid-stride sweeps
 constexpr int kPointSums = 6;    // per-block FP64 partial sums of the point pass
 constexpr int kEdgeSums = 3;     // per-block FP64 partial sums of the edge pass
 constexpr int kIterSums = kPointSums + kEdgeSums;
-constexpr int kEdgeBlock = 1024; // threads per block of the edge-stage kernels
+constexpr int kEdgeBlock = 512;  // threads per block of the edge-stage kernels
 constexpr int kEdgeWaves = kEdgeBlock / kWave;
 constexpr int kEsumRows = 512;   // max partial rows the edge stage leaves
 constexpr int kEsumStride = 10;  // doubles per partial row (kIterSums, padded to 16 B)
