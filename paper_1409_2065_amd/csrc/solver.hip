@@ -20,11 +20,16 @@
 //             (group soft-threshold) are recomputed on the fly from the edge
 //             norms and d of iteration m-1.  Per-block FP64 partial sums feed
 //             d, the objective and the stopping test.
-//   k_edge_fused (rows up to 1024 wide) or k_edge_slab / k_edge_tiles and
+//   k_edge_items (rows up to 1024 wide: work items of edges sharing a lower
+//             end) or k_edge_slab_items / k_edge_slab / k_edge_tiles and
 //             k_edge_reduce (wider rows): per edge ||b_e|| of the new A, the
 //             terms of ||V - D A||^2 and of the penalty, and the q factors of
 //             the next sweep; each block also gathers a fixed subset of the
 //             point sweep's block partials into its partial row.
+//
+// Storage: the mixed precision keeps A as its FP32 gather copy plus an FP32
+// low half; single solves with one projection sweep do not store U during
+// the solve where nothing reads it (k_u_finish rebuilds it at the end).
 //
 // ||V - D A||^2 is assembled as sum_e s_e^2 ||b'_e||^2
 //   - 2 sum_i <h_i, a_i> + sum_e ||b_e||^2, with h_i = sum_j s_ij (a'_i - a'_j)
