@@ -109,3 +109,37 @@ def test_lazy_u_no_mask_plain(cc, monkeypatch):
     prob = (X, M, E, w)
     _same(_run(cc, prob, "mixed", STEPS, monkeypatch, "0"),
           _run(cc, prob, "mixed", STEPS, monkeypatch, "1"))
+
+
+@pytest.mark.parametrize("precision", ["f32", "mixed", "f64"])
+def test_state_storage_rounding(cc, precision):
+    """The state a problem stores: U in the state type; A in FP32 (f32), as
+    an FP32 high half plus an FP32 low half (mixed: 48 significant bits, the
+    high half being the nearest FP32 value), or in FP64.  Reading the state
+    back and setting it again reproduces it bit for bit."""
+    X, M, E, w, _ = reduced_expression(n=120, p=70)
+    rng = np.random.default_rng(7)
+    U0 = rng.standard_normal((120, 70)) * np.exp(rng.uniform(-20, 20, (120, 70)))
+    A0 = rng.standard_normal((120, 70)) * np.exp(rng.uniform(-20, 20, (120, 70)))
+    s0 = rng.uniform(0.0, 1.0, len(E))
+    with _gpu(cc, X, M, E, w, precision) as g:
+        g.set_state(torch.tensor(U0, device="cuda"), torch.tensor(A0, device="cuda"),
+                    torch.tensor(s0, device="cuda"))
+        U1, A1, s1 = (t.cpu().numpy() for t in g.get_state())
+        g.set_state(torch.tensor(U1, device="cuda"), torch.tensor(A1, device="cuda"),
+                    torch.tensor(s1, device="cuda"))
+        U2, A2, s2 = (t.cpu().numpy() for t in g.get_state())
+    assert np.array_equal(s1, s0)
+    assert np.array_equal(U2, U1) and np.array_equal(A2, A1) and np.array_equal(s2, s1)
+    if precision == "f32":
+        assert np.array_equal(U1, U0.astype(np.float32).astype(np.float64))
+        assert np.array_equal(A1, A0.astype(np.float32).astype(np.float64))
+    elif precision == "f64":
+        assert np.array_equal(U1, U0) and np.array_equal(A1, A0)
+    else:
+        assert np.array_equal(U1, U0)
+        hi = A0.astype(np.float32).astype(np.float64)
+        lo = (A0 - hi).astype(np.float32).astype(np.float64)
+        assert np.array_equal(A1, hi + lo)
+        assert np.array_equal(A1.astype(np.float32).astype(np.float64), hi)
+        assert np.max(np.abs(A1 - A0) / np.abs(A0)) <= 2.0 ** -47
