@@ -350,7 +350,8 @@ cc_status cc_components(int64_t n, int64_t n_edges, const int32_t *ei,
  * iterations of each point-sweep tile width (64, 128, 256 features) with
  * about 1, 4 and 16 work items per wave (a wave with several prefetches the
  * next), and keeps the fastest; it leaves every problem at its initial
- * state.  The
+ * state.  The batched edge sweep takes 4 work items per wave whatever that
+ * choice.  The
  * batch refers to the problems (it does not own them): destroy the batch
  * first.  A problem's solver state belongs to the batch while it runs.
  *

@@ -3286,6 +3286,8 @@ static void free_launch_set(LaunchSet &L) {
 // (waves with several items prefetch the next); point launches are grouped
 // by (vec, ipw), edge launches by each instance's features per lane.  Sets
 // the problems' tile fields and scalar slot 0.
+constexpr int kBatchEdgeItems = 4;  // items per wave of the batched item edge sweep
+
 static cc_status build_launch_set(LaunchSet &L, const std::vector<Problem *> &probs,
                                   const std::vector<const BatchInst *> &bis,
                                   const std::vector<int> &order, const std::vector<int> &vec_of,
@@ -3302,10 +3304,13 @@ static cc_status build_launch_set(LaunchSet &L, const std::vector<Problem *> &pr
     P->ntile = (int)cdiv(P->ld, P->tile_w);
     P->cur_K = K;
     P->ipw = ipw_of[b];
-    P->eipw = ipw_of[b];
+    // the item edge sweep takes kBatchEdgeItems items per wave whatever the
+    // point sweep's choice (measured: 4 against 1 and 16, and against
+    // following the point sweep)
+    P->eipw = kBatchEdgeItems;
     P->nbe = edge_rows(P);
     const Launch Lp = sweep_grid(P->n * P->ntile, kPointWaves, P->ipw);
-    const Launch Li = edge_items_grid(P->n_items, P->ipw);
+    const Launch Li = edge_items_grid(P->n_items, P->eipw);
     pblocks[b] = Lp.blocks;
     eblocks[b] = Li.blocks;
     for (int par = 0; par < 2; ++par) {

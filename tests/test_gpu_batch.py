@@ -46,6 +46,7 @@ def test_batch_equals_alone_bitwise(cc, monkeypatch):
     ids = [31, 33, 37, 22]
     inst = [instance(b) for b in ids]
     monkeypatch.setenv("CCMI_VEC", "4")
+    monkeypatch.setenv("CCMI_EDGE_IPW", "4")  # the batched edge sweep's items per wave
     ref = [alone(cc, X, e, w, g) for X, e, w, g in inst]
     probs = [make(cc, X, e, w) for X, e, w, _ in inst]
     with cc.Batch(probs, [g for *_, g in inst], autotune=False, **OPTS) as bt:

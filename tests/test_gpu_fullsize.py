@@ -211,6 +211,7 @@ def test_batched_full_size_sampled_instances_equal_alone(cc, monkeypatch):
         monkeypatch.setenv("CCMI_VEC", str(cfg["vec"]))
         exact = cfg["items_per_wave"] in (1, 4)
         monkeypatch.setenv("CCMI_IPW", str(cfg["items_per_wave"] if exact else 1))
+        monkeypatch.setenv("CCMI_EDGE_IPW", "4")  # the batched edge sweep's items per wave
         p, g = make(b)
         with p:
             rinf, rlab, _ = p.solve_path(g, labels=True, **opts)
