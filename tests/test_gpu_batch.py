@@ -41,14 +41,15 @@ def alone(cc, X, edges, w, gammas, precision="mixed"):
     return infos, lab.cpu().numpy(), U, A, s
 
 
-def test_batch_equals_alone_bitwise(cc, monkeypatch):
+@pytest.mark.parametrize("precision", ["f32", "mixed", "f64"])
+def test_batch_equals_alone_bitwise(cc, monkeypatch, precision):
     # p in (128, 256]: both sweeps take 4 features per lane alone and batched
     ids = [31, 33, 37, 22]
     inst = [instance(b) for b in ids]
     monkeypatch.setenv("CCMI_VEC", "4")
     monkeypatch.setenv("CCMI_EDGE_IPW", "4")  # the batched edge sweep's items per wave
-    ref = [alone(cc, X, e, w, g) for X, e, w, g in inst]
-    probs = [make(cc, X, e, w) for X, e, w, _ in inst]
+    ref = [alone(cc, X, e, w, g, precision) for X, e, w, g in inst]
+    probs = [make(cc, X, e, w, precision) for X, e, w, _ in inst]
     with cc.Batch(probs, [g for *_, g in inst], autotune=False, **OPTS) as bt:
         assert bt.config()["vec"] == 4
         labs, infos, lat = bt.run()

@@ -30,11 +30,11 @@ def request(seed, n, p, clusters, missing):
     return X, mask
 
 
-def alone(cc, X, mask, k=10, phi=-0.5):
+def alone(cc, X, mask, k=10, phi=-0.5, precision="mixed"):
     Xt = torch.tensor(X * (mask if mask is not None else 1), dtype=torch.float32, device="cuda")
     M = None if mask is None else torch.tensor(mask, device="cuda")
     e, w, _ = cc.build_knn_weights(Xt, M, k=k, phi=phi)
-    with cc.Problem(Xt, M, e, w, precision="mixed") as pr:
+    with cc.Problem(Xt, M, e, w, precision=precision) as pr:
         infos, lab, _ = pr.solve_path(GAMMAS, labels=True, **OPTS)
         U = pr.U().cpu().numpy()
     return lab.cpu().numpy(), infos, U
@@ -44,9 +44,10 @@ def alone(cc, X, mask, k=10, phi=-0.5):
 SPECS = [(11, 60, 20, 3, 0.0), (12, 150, 300, 4, 0.1), (13, 90, 700, 3, 0.1), (14, 200, 40, 5, 0.0)]
 
 
-def test_server_mix_equals_alone(cc):
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+def test_server_mix_equals_alone(cc, precision):
     reqs = [request(*s) for s in SPECS]
-    with cc.Server("mixed", hbm_budget=8 << 30, round_iters=32, **OPTS) as srv:
+    with cc.Server(precision, hbm_budget=8 << 30, round_iters=32, **OPTS) as srv:
         tickets = [srv.submit(X, m, k=10, phi=-0.5, gammas=GAMMAS) for X, m in reqs[:2]]
         srv.step()
         srv.step()
@@ -66,7 +67,7 @@ def test_server_mix_equals_alone(cc):
             srv.release(t)
     for (X, m), t in zip(reqs, tickets):
         lab, infos, U = states[t]
-        rlab, rinf, rU = alone(cc, X, m)
+        rlab, rinf, rU = alone(cc, X, m, precision=precision)
         for k in range(len(GAMMAS)):
             assert infos[k]["converged"] == rinf[k]["converged"], (t, k)
             if rinf[k]["converged"]:
