@@ -71,10 +71,11 @@ def test_lazy_u_narrow_tiles(cc, vec, monkeypatch):
           _run(cc, prob, "mixed", STEPS[:3], monkeypatch, "2"))
 
 
-def test_lazy_u_several_items_per_wave(cc, monkeypatch):
-    """3000 points x 3 tiles in blocks of 4 waves: waves take several items
-    and prefetch (the default takes the lazy path here)."""
-    monkeypatch.setenv("CCMI_POINT_WAVES", "4")
+@pytest.mark.parametrize("waves", ["4", "8"])
+def test_lazy_u_several_items_per_wave(cc, monkeypatch, waves):
+    """3000 points x 3 tiles in blocks of 4 and 8 waves: waves take several
+    items and prefetch (the default takes the lazy path here)."""
+    monkeypatch.setenv("CCMI_POINT_WAVES", waves)
     X, M, E, w, _ = reduced_expression(n=3000, p=700)
     prob = (X, M, E, w)
     steps = [(5.0, dict(tol=0.0, max_iter=12)), (6.0, dict(tol=0.0, max_iter=5))]

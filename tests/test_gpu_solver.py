@@ -490,10 +490,12 @@ def test_non_finite_state_reports_numeric_error(cc):
         assert np.array_equal(g.U(torch.float64).cpu().numpy(), Uref)
 
 
-def test_point_sweep_prefetch_mixed_wide_blocks(cc):
+@pytest.mark.parametrize("waves", ["4", "8", "16"])
+def test_point_sweep_prefetch_mixed_wide_blocks(cc, waves, monkeypatch):
     """The mixed precision with several items per wave (3000 points x 3
-    tiles) runs the point sweep in 8-wave blocks: trajectory within the
+    tiles) in point-sweep blocks of 4, 8 and 16 waves: trajectory within the
     mixed bar with the same fused edges."""
+    monkeypatch.setenv("CCMI_POINT_WAVES", waves)
     X, M, E, w, _ = reduced_expression(n=3000, p=700)
     st, _ = oracle_jacobi(X, M, E, w).solve(5.0, mm.Opts(tol=0, max_iter=12, proj="jacobi:1"))
     with _gpu(cc, X, M, E, w, "mixed") as g:
