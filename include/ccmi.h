@@ -201,8 +201,10 @@ cc_status cc_solve(cc_problem_t prob, double gamma, const cc_solve_opts *opts,
  * label of every case after gammas[g], the smallest case index of its
  * cluster.  U_path (device float32, n_gamma rows of n*p, row-major with
  * leading dimension p, may be NULL): the centres after each gamma.
- * infos (host, n_gamma entries, may be NULL).  Stops at the first gamma
- * whose solve fails and returns its status (infos up to it are filled). */
+ * infos (host, n_gamma entries, may be NULL).  Every gamma must be finite
+ * and >= 0: all are checked before the first is solved (CC_ERR_INVALID_ARG,
+ * state untouched).  Stops at the first gamma whose solve fails and returns
+ * its status (infos up to it are filled). */
 cc_status cc_solve_path(cc_problem_t prob, int32_t n_gamma,
                         const double *gammas, const cc_solve_opts *opts,
                         int32_t *labels, float *U_path, cc_solve_info *infos);

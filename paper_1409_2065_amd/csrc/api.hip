@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -147,7 +148,10 @@ cc_status cc_solve_path(cc_problem_t prob, int32_t n_gamma, const double *gammas
   if (n_gamma < 0 || (n_gamma > 0 && !gammas)) { set_error("bad gamma array"); return CC_ERR_INVALID_ARG; }
   if (!opts_ok(opts)) { set_error("opts->struct_size mismatch"); return CC_ERR_INVALID_ARG; }
   for (int32_t g = 0; g < n_gamma; ++g)
-    if (!(gammas[g] >= 0.0)) { set_error("gammas must be >= 0"); return CC_ERR_INVALID_ARG; }
+    if (!(gammas[g] >= 0.0) || !std::isfinite(gammas[g])) {
+      set_error("gammas must be finite and >= 0");
+      return CC_ERR_INVALID_ARG;
+    }
   Problem *P = reinterpret_cast<Problem *>(prob);
   cc_solve_opts o = resolve(opts);
   for (int32_t g = 0; g < n_gamma; ++g) {
@@ -181,7 +185,10 @@ cc_status cc_solve_path_pc(cc_problem_t prob, int32_t n_gamma, const double *gam
   if (!opts_ok(opts)) { set_error("opts->struct_size mismatch"); return CC_ERR_INVALID_ARG; }
   if (r < 1 || r > 16 || !V || !proj) { set_error("need 1 <= r <= 16 and V, proj"); return CC_ERR_INVALID_ARG; }
   for (int32_t g = 0; g < n_gamma; ++g)
-    if (!(gammas[g] >= 0.0)) { set_error("gammas must be >= 0"); return CC_ERR_INVALID_ARG; }
+    if (!(gammas[g] >= 0.0) || !std::isfinite(gammas[g])) {
+      set_error("gammas must be finite and >= 0");
+      return CC_ERR_INVALID_ARG;
+    }
   Problem *P = reinterpret_cast<Problem *>(prob);
   cc_solve_opts o = resolve(opts);
   for (int32_t g = 0; g < n_gamma; ++g) {

@@ -214,6 +214,14 @@ def test_invalid_inputs_rejected(cc):
     with cc.Problem(Xb, mb, e, wt) as g:
         g.solve(1.0, max_iter=5)
         assert torch.isfinite(g.U()).all()
+        # a path with an infinite or negative gamma is refused before any
+        # gamma is solved: the state stays as it was
+        U0 = [t.cpu().numpy() for t in g.get_state()]
+        for bad in ([2.0, float("inf")], [2.0, -1.0], [2.0, float("nan")]):
+            with pytest.raises(cc.CCError) as ei:
+                g.solve_path(bad, max_iter=5)
+            assert ei.value.status == 1
+            assert all(np.array_equal(a, b) for a, b in zip(U0, (t.cpu().numpy() for t in g.get_state())))
     with pytest.raises(cc.CCError):
         _gpu(cc, X, None, E[:, ::-1].copy(), w, "mixed")   # i > j
     with pytest.raises(cc.CCError):
