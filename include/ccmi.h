@@ -283,7 +283,13 @@ cc_status cc_get_state(cc_problem_t prob, double *U, double *A, int64_t ld,
  * those of j (self excluded, distance ties to the lower index).  Distances
  * use the matrix with missing entries replaced by observed column means.
  * Candidates are ranked with a Gram matrix product on the matrix cores and
- * then re-ranked with exact FP64 distances.
+ * then re-ranked with exact FP64 distances.  The result is exact: a row is
+ * accepted only when its k-th FP64 distance lies below the smallest FP32
+ * distance left out minus a bound on that distance's rounding error;
+ * otherwise the row is ranked again over 8x more candidates (at least 512),
+ * then over all rows (n <= 12289).  CC_ERR_NUMERIC when a row still cannot
+ * be certified (only above that n, for rows with more than 12288 others
+ * within FP32 rounding of their k-th neighbour).
  *   k           1 <= k < n.
  *   phi         >= 0 literal; < 0 means |phi| / median(d^2 over the edge
  *               set), the lower median.

@@ -198,11 +198,23 @@ __device__ inline uint32_t float_key(float f) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-// Per row: bitonic sort of (key(d2) << 32 | j) in LDS; keep the first K.
+// Most candidates k_recheck takes per row (12 bytes of LDS each).
+constexpr int64_t kRecheckMaxK = 12288;
+
+// Inverse of float_key.
+__device__ inline float key_float(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// Per row: bitonic sort of (key(d2) << 32 | j) in LDS; keep the first K, and
+// in dnext the FP32 d2 of the first row left out (infinity when none is).
+// todo (may be NULL): only rows with todo[i] != 0.
 __global__ __launch_bounds__(1024) void k_row_candidates(int n, const float *D2, int64_t ldd,
-                                                         int npow2, int K, int32_t *cand) {
+                                                         int npow2, int K, int32_t *cand,
+                                                         const int *todo, float *dnext) {
   extern __shared__ unsigned long long keys[];
   const int i = blockIdx.x;
+  if (todo && !todo[i]) return;
   for (int j = threadIdx.x; j < npow2; j += blockDim.x) {
     unsigned long long key = ~0ull;
     if (j < n && j != i) key = ((unsigned long long)float_key(D2[(size_t)i * ldd + j]) << 32) | (unsigned)j;
@@ -222,14 +234,40 @@ __global__ __launch_bounds__(1024) void k_row_candidates(int n, const float *D2,
     }
   }
   for (int r = threadIdx.x; r < K; r += blockDim.x) cand[(size_t)i * K + r] = (int32_t)(keys[r] & 0xffffffffu);
+  if (threadIdx.x == 0) dnext[i] = K < n - 1 ? key_float((uint32_t)(keys[K] >> 32)) : INFINITY;
+}
+
+// Largest FP32 row norm of the n rows.
+__global__ __launch_bounds__(1024) void k_max_norm(int n, const float *nrm, float *nmax) {
+  __shared__ float s[1024];
+  float m = 0.f;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, nrm[i]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *nmax = s[0];
 }
 
 // Exact FP64 squared distances of the candidates, then the k best by (d2, j).
+// Certificate: every row left out has an FP32 distance of at least dnext[i],
+// so an exact one of at least dnext[i] - bound, with bound = bscale *
+// (|x_i|^2 + max_j |x_j|^2) covering the rounding of the FP32 Gram product,
+// the norms, their combination and the FP32 copy of X~.  The k best
+// candidates are then the k nearest of all rows when the k-th exact distance
+// lies below that; otherwise uncert[i] = 1 and the row is counted in *n_uncert.
+// todo (may be NULL): only rows with todo[i] != 0.
 __global__ __launch_bounds__(256) void k_recheck(int n, int p, const double *Xd, int K, int k,
-                                                 const int32_t *cand, int32_t *knn) {
+                                                 const int32_t *cand, int32_t *knn, const int *todo,
+                                                 const float *dnext, const float *nrm,
+                                                 const float *nmax, double bscale, int *uncert,
+                                                 int *n_uncert) {
   extern __shared__ double sd[];  // K doubles + K ints
   int *sj = reinterpret_cast<int *>(sd + K);
   const int i = blockIdx.x;
+  if (todo && !todo[i]) return;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
   for (int c = wave; c < K; c += nw) {
@@ -253,6 +291,10 @@ __global__ __launch_bounds__(256) void k_recheck(int n, int p, const double *Xd,
       const int tj = sj[r]; sj[r] = sj[best]; sj[best] = tj;
       knn[(size_t)i * k + r] = sj[r];
     }
+    const double bound = bscale * ((double)nrm[i] + (double)*nmax);
+    const bool ok = sd[k - 1] < (double)dnext[i] - bound;
+    uncert[i] = ok ? 0 : 1;
+    if (!ok) atomicAdd(n_uncert, 1);
   }
 }
 
@@ -536,16 +578,56 @@ static cc_status knn_lists(int64_t n, int64_t p, const TI *X, int64_t ldx, const
                        (int)n_pad, nsplit, part.as<float>(), nrm.as<float>(), D2.as<float>(),
                        (int64_t)n);
   CC_HIP(hipGetLastError());
+  // rounding bound of the FP32 distances (see k_recheck): (2 m + 24) u with
+  // m the longest FP32 accumulation (ldk products and the split combine)
+  const double bscale = (2.0 * (double)(ldk + nsplit) + 24.0) * std::ldexp(1.0, -24) * 1.001;
+  DevBuf dnext, nmax, uncert, nun;
+  KN_TRY(dnext.alloc(n * 4));
+  KN_TRY(nmax.alloc(4));
+  KN_TRY(uncert.alloc(n * 4));
+  KN_TRY(nun.alloc(4));
+  hipLaunchKernelGGL(k_max_norm, dim3(1), dim3(1024), 0, st, (int)n, nrm.as<float>(), nmax.as<float>());
   const size_t lds = (size_t)npow2 * 8;
   CC_HIP(hipFuncSetAttribute((const void *)k_row_candidates,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_row_candidates, dim3((int)n), dim3(1024), lds, st, (int)n,
-                     D2.as<float>(), (int64_t)n, npow2, K, cand.as<int32_t>());
-  CC_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_recheck, dim3((int)n), dim3(256), (size_t)K * 12, st, (int)n, (int)p,
-                     Xd.as<double>(), K, (int)k, cand.as<int32_t>(), knn.as<int32_t>());
-  CC_HIP(hipGetLastError());
-  return CC_OK;
+  // wider passes for the rows a pass could not certify: 8 K (at least 512)
+  // candidates, then all rows up to kRecheckMaxK (every row for n up to
+  // kRecheckMaxK + 1, which certifies by construction)
+  const int64_t widths[3] = {K, std::min<int64_t>({n - 1, std::max<int64_t>(8 * (int64_t)K, 512), kRecheckMaxK}),
+                             std::min<int64_t>(n - 1, kRecheckMaxK)};
+  const int *todo = nullptr;
+  DevBuf cand2;
+  int Kp = K;
+  int32_t *cp = cand.as<int32_t>();
+  for (int pass = 0; pass < 3; ++pass) {
+    if (pass > 0) {
+      if (widths[pass] <= Kp) continue;
+      Kp = (int)widths[pass];
+      if (cand2.p) { (void)hipFree(cand2.p); cand2.p = nullptr; }
+      KN_TRY(cand2.alloc((size_t)n * Kp * 4));
+      cp = cand2.as<int32_t>();
+      todo = uncert.as<int>();
+    }
+    CC_HIP(hipMemsetAsync(nun.p, 0, 4, st));
+    hipLaunchKernelGGL(k_row_candidates, dim3((int)n), dim3(1024), lds, st, (int)n,
+                       D2.as<float>(), (int64_t)n, npow2, Kp, cp, todo, dnext.as<float>());
+    CC_HIP(hipGetLastError());
+    const size_t lds2 = (size_t)Kp * 12;
+    CC_HIP(hipFuncSetAttribute((const void *)k_recheck, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)std::max<size_t>(lds2, 1)));
+    hipLaunchKernelGGL(k_recheck, dim3((int)n), dim3(256), lds2, st, (int)n, (int)p,
+                       Xd.as<double>(), Kp, (int)k, cp, knn.as<int32_t>(), todo,
+                       dnext.as<float>(), nrm.as<float>(), nmax.as<float>(), bscale,
+                       uncert.as<int>(), nun.as<int>());
+    CC_HIP(hipGetLastError());
+    int hn = 0;
+    CC_HIP(hipMemcpyAsync(&hn, nun.p, 4, hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    if (hn == 0) return CC_OK;
+  }
+  set_error("kNN: the nearest neighbours of some rows could not be certified exact "
+            "(FP32 distances too close to separate them)");
+  return CC_ERR_NUMERIC;
 }
 
 // Step 6 over E edges with squared distances d2 (device): phi (literal, or

@@ -58,6 +58,21 @@ def test_knn_small_and_ragged(cc, n):
         _check(cc, X, None, 3, 0.3)
 
 
+@pytest.mark.parametrize("n", [300, 1500])
+def test_knn_near_duplicates_exact(cc, n):
+    """A third of the rows are copies of one row plus noise far below the
+    FP32 rounding of their distances, so the FP32 Gram product cannot rank
+    them.  The FP64 re-rank of the first candidates cannot be certified for
+    those rows; the wider pass (every row for n = 300, 512 candidates for
+    n = 1500) can, and the edge set equals the oracle's exact one."""
+    rng = np.random.default_rng(7)
+    p = 256
+    X = rng.normal(size=(n, p)) * 3.0 + 10.0
+    dup = n // 3
+    X[:dup] = X[0] + rng.normal(size=(dup, p)) * 1e-4
+    _check(cc, as_f32_values(X), None, 6, 0.0)
+
+
 def test_knn_ties_lower_index(cc):
     X = np.arange(9, dtype=np.float64)[:, None]  # equal spacing: every row has a tie
     _check(cc, X, None, 1, 0.0)
