@@ -198,8 +198,10 @@ __device__ inline uint32_t float_key(float f) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-// Most candidates k_recheck takes per row (12 bytes of LDS each).
+// Most candidates k_recheck takes per row (12 bytes of LDS each), and the
+// largest n of the kNN builders (a row's sort keys fill 8 * n bytes of LDS).
 constexpr int64_t kRecheckMaxK = 12288;
+constexpr int64_t kKnnMaxN = 16384;
 
 // Inverse of float_key.
 __device__ inline float key_float(uint32_t k) {
@@ -587,9 +589,13 @@ static cc_status knn_lists(int64_t n, int64_t p, const TI *X, int64_t ldx, const
   KN_TRY(uncert.alloc(n * 4));
   KN_TRY(nun.alloc(4));
   hipLaunchKernelGGL(k_max_norm, dim3(1), dim3(1024), 0, st, (int)n, nrm.as<float>(), nmax.as<float>());
+  // the dynamic LDS limits are set to the largest sizes these kernels take
+  // (the same values on every call, so that concurrent builds agree)
   const size_t lds = (size_t)npow2 * 8;
   CC_HIP(hipFuncSetAttribute((const void *)k_row_candidates,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kKnnMaxN * 8)));
+  CC_HIP(hipFuncSetAttribute((const void *)k_recheck, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(kRecheckMaxK * 12)));
   // wider passes for the rows a pass could not certify: 8 K (at least 512)
   // candidates, then all rows up to kRecheckMaxK (every row for n up to
   // kRecheckMaxK + 1, which certifies by construction)
@@ -613,8 +619,6 @@ static cc_status knn_lists(int64_t n, int64_t p, const TI *X, int64_t ldx, const
                        D2.as<float>(), (int64_t)n, npow2, Kp, cp, todo, dnext.as<float>());
     CC_HIP(hipGetLastError());
     const size_t lds2 = (size_t)Kp * 12;
-    CC_HIP(hipFuncSetAttribute((const void *)k_recheck, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)std::max<size_t>(lds2, 1)));
     hipLaunchKernelGGL(k_recheck, dim3((int)n), dim3(256), lds2, st, (int)n, (int)p,
                        Xd.as<double>(), Kp, (int)k, cp, knn.as<int32_t>(), todo,
                        dnext.as<float>(), nrm.as<float>(), nmax.as<float>(), bscale,
@@ -747,7 +751,7 @@ cc_status min_connected_k(int64_t n, int64_t p, int32_t x_dtype, const void *X, 
                           const uint8_t *mask, int64_t ldm, int32_t k_max, int32_t *k_min,
                           int32_t *n_components, hipStream_t stream) {
   if (n < 2 || p < 1) { set_error("need n >= 2 and p >= 1"); return CC_ERR_INVALID_ARG; }
-  if (n > 16384) { set_error("cc_min_connected_k supports n <= 16384"); return CC_ERR_INVALID_ARG; }
+  if (n > kKnnMaxN) { set_error("cc_min_connected_k supports n <= 16384"); return CC_ERR_INVALID_ARG; }
   if ((int64_t)n * p > ((int64_t)1 << 31) - 1) { set_error("n * p too large"); return CC_ERR_INVALID_ARG; }
   if (k_max < 1 || k_max >= n || k_max > 1024) { set_error("need 1 <= k_max < n and k_max <= 1024"); return CC_ERR_INVALID_ARG; }
   if ((int64_t)n * k_max > ((int64_t)1 << 31) - 1) { set_error("n * k_max too large"); return CC_ERR_INVALID_ARG; }
@@ -849,7 +853,7 @@ cc_status build_knn_weights(int64_t n, int64_t p, int32_t x_dtype, const void *X
                             int64_t capacity, int64_t *n_edges, double *phi_used,
                             hipStream_t stream) {
   if (n < 2 || p < 1) { set_error("need n >= 2 and p >= 1"); return CC_ERR_INVALID_ARG; }
-  if (n > 16384) { set_error("cc_build_knn_weights supports n <= 16384"); return CC_ERR_INVALID_ARG; }
+  if (n > kKnnMaxN) { set_error("cc_build_knn_weights supports n <= 16384"); return CC_ERR_INVALID_ARG; }
   if ((int64_t)n * p > ((int64_t)1 << 31) - 1) { set_error("n * p too large"); return CC_ERR_INVALID_ARG; }
   if (k < 1 || k >= n) { set_error("need 1 <= k < n"); return CC_ERR_INVALID_ARG; }
   if (!X || !ei || !ej || !w || !n_edges) { set_error("NULL argument"); return CC_ERR_INVALID_ARG; }
