@@ -73,6 +73,21 @@ def test_knn_near_duplicates_exact(cc, n):
     _check(cc, as_f32_values(X), None, 6, 0.0)
 
 
+def test_knn_uncertifiable_rows_are_an_error(cc):
+    """n above what the widest pass ranks exhaustively (12289 rows), with
+    every row within FP32 rounding of every other: no row's neighbours can
+    be certified exact, and the builder returns CC_ERR_NUMERIC instead of
+    an edge set."""
+    rng = np.random.default_rng(3)
+    n, p = 16384, 8
+    X = 1.0 + rng.normal(size=(n, p)) * 1e-4
+    Xt = torch.tensor(X, dtype=torch.float32, device="cuda")
+    with pytest.raises(cc.CCError) as ei:
+        cc.build_knn_weights(Xt, None, k=6, phi=0.0)
+    assert ei.value.status == 4  # CC_ERR_NUMERIC
+    assert "certified" in str(ei.value)
+
+
 def test_knn_ties_lower_index(cc):
     X = np.arange(9, dtype=np.float64)[:, None]  # equal spacing: every row has a tie
     _check(cc, X, None, 1, 0.0)
